@@ -1,0 +1,303 @@
+/*
+ * smmo.h — C-ABI of the MI355X SMMO object heap (DynaSOAr method).
+ *
+ * Method: Springer & Masuhara, "DynaSOAr: A Parallel Memory Allocator for
+ * Object-oriented Programming on GPUs with Efficient Memory Access", ECOOP
+ * 2019 (arXiv 1810.11765).  Sec. 2.1 lists the operations this library
+ * exports: parallel_do, parallel_new, device-side new / destroy, device_do.
+ *
+ * Conventions for every entry point
+ *  - Return 0 on success or a negative SMMO_E* code; smmo_last_error() gives a
+ *    message for the calling thread's last failure.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call is asynchronous on that stream unless it says "synchronizes".
+ *  - Device pointers are addresses in the current HIP device's memory; host
+ *    pointers are ordinary process memory.  No call allocates device memory:
+ *    the caller hands in one device buffer per heap and owns it.
+ *  - Handles (smmo_heap*) are not thread-safe; one stream per heap at a time.
+ */
+#ifndef SMMO_H
+#define SMMO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ limits ---- */
+#define SMMO_MAX_CLASSES 16       /* class ids 0..15 (the paper's 8-bit type id, Sec. 3.3) */
+#define SMMO_MAX_FIELDS 16        /* fields per class */
+#define SMMO_MAX_LEVELS 6         /* bitmap levels: 64^6 blocks */
+#define SMMO_ARGS_MAX 256         /* bytes of a method / constructor argument blob */
+
+/* ------------------------------------------------------------ errors ---- */
+#define SMMO_OK 0
+#define SMMO_EINVAL (-1)          /* bad descriptor, class id, method id or size */
+#define SMMO_ETOOSMALL (-2)       /* dev_bytes below smmo_heap_bytes() */
+#define SMMO_ENOMEM_DEVICE (-3)   /* the heap ran out of blocks (sticky status) */
+#define SMMO_ERETRY (-4)          /* a bounded retry loop gave up (sticky status) */
+#define SMMO_EHIP (-5)            /* a HIP runtime call failed; see smmo_last_error() */
+#define SMMO_ECORRUPT (-6)        /* a precondition violation was detected on the device */
+#define SMMO_ENOTBUILT (-7)       /* requested kernel variant not compiled in */
+
+/* Sticky device status bits (smmo_status). */
+#define SMMO_STATUS_OOM 1u        /* an allocation found no active and no free block */
+#define SMMO_STATUS_RETRY 2u      /* a spinning bitmap set/clear exceeded its bound */
+#define SMMO_STATUS_CORRUPT 4u    /* e.g. destroy of a slot that is not live */
+
+/* ------------------------------------------------------------- types ---- */
+
+/* One class: its fields' byte sizes in declaration order (each 1, 2, 4 or 8). */
+typedef struct smmo_class_desc {
+    uint32_t nfields;
+    const uint8_t* field_bytes;   /* host array of nfields sizes */
+} smmo_class_desc;
+
+/* Layout of one class inside a block (Sec. 3.2; SOA arrays 128-B aligned). */
+typedef struct smmo_layout {
+    uint32_t capacity;                       /* N_T = floor(64*size(T_s)/size(T)) */
+    uint32_t nfields;
+    uint64_t block_bytes;                    /* bytes of every block's data segment */
+    uint32_t field_bytes[SMMO_MAX_FIELDS];
+    uint32_t field_offset[SMMO_MAX_FIELDS];  /* byte offset of the field's SOA array */
+} smmo_layout;
+
+typedef struct smmo_heap smmo_heap;          /* opaque host handle */
+
+/*
+ * Raw heap metadata, the first bytes of the device buffer and of
+ * smmo_dump_raw's output.  All integers little-endian.  Byte offsets are from
+ * the start of the device buffer.
+ *   type[M]   uint32 block type id (0xFFFFFFFF: never initialized)
+ *   alloc[M]  uint64 object allocation bitmap of each block (Sec. 3.1)
+ *   iter[M]   uint64 object iteration bitmap of each block (Sec. 3.1)
+ *   bitmaps   uint64 words; bitmap b (0 = free, 1+T = allocated[T],
+ *             1+ncls+T = active[T], Sec. 3.4) starts at word b*bitmap_words;
+ *             its level l (0 = containers of block bits) starts
+ *             level_off[l] words further and has level_words[l] words.
+ *             Bit i of level l+1 is the OR of word i of level l (Sec. 4.1.1).
+ *   data      block b's data segment is at off_data + b*block_bytes.
+ */
+#define SMMO_MAGIC 0x504145484F4D4D53ull /* "SMMOHEAP" in little-endian bytes */
+typedef struct smmo_raw_header {
+    uint64_t magic;
+    uint64_t version;                        /* 1 */
+    uint64_t num_blocks;                     /* M */
+    uint64_t ncls;
+    uint64_t block_bytes;
+    uint64_t nlevels;
+    uint64_t level_words[SMMO_MAX_LEVELS];
+    uint64_t level_off[SMMO_MAX_LEVELS];
+    uint64_t bitmap_words;
+    uint64_t off_status;                     /* uint32 status, then uint64 counters[16] at +64 */
+    uint64_t off_type;
+    uint64_t off_alloc;
+    uint64_t off_iter;
+    uint64_t off_bitmaps;
+    uint64_t off_scratch;
+    uint64_t scratch_bytes;
+    uint64_t off_data;                       /* = raw dump size */
+    uint64_t total_bytes;
+    uint64_t capacity[SMMO_MAX_CLASSES];
+    uint64_t nfields[SMMO_MAX_CLASSES];
+    uint32_t field_bytes[SMMO_MAX_CLASSES][SMMO_MAX_FIELDS];
+    uint32_t field_off[SMMO_MAX_CLASSES][SMMO_MAX_FIELDS];
+    uint32_t tune_flags;                     /* SMMO_TUNE_* */
+    uint32_t lookups;                        /* active-block lookup attempts r (Sec. 4.2) */
+    uint32_t force_fail_ppm;                 /* fault injection rate of try_find_set */
+    uint32_t reserved0;
+} smmo_raw_header;
+
+/* Device counters (SMMO_TUNE_STATS), uint64 at off_status + 64. */
+enum smmo_counter {
+    SMMO_CNT_ALLOC_OBJ = 0,     /* objects allocated by the device allocator */
+    SMMO_CNT_FREE_OBJ,          /* objects destroyed */
+    SMMO_CNT_BLOCK_INIT,        /* slow paths: blocks initialized (Alg. 1 slow path) */
+    SMMO_CNT_BLOCK_FREE,        /* successful invalidations (Alg. 9) */
+    SMMO_CNT_INVAL_ROLLBACK,    /* invalidation rollbacks */
+    SMMO_CNT_TYPE_ROLLBACK,     /* reservations rolled back after a type change */
+    SMMO_CNT_FIND_FAIL,         /* active-block lookups that failed */
+    SMMO_CNT_RESERVE_FAIL,      /* reservations that got no slot */
+    SMMO_CNT_SPIN,              /* retries of spinning set/clear */
+    SMMO_CNT_RESERVE_ATOMIC,    /* atomic ORs on allocation bitmaps */
+    SMMO_CNT_NUM = 16
+};
+
+/* Tuning / ablation / fault-injection flags (smmo_set_tuning). */
+#define SMMO_TUNE_NO_ROTATE 1u      /* plain find-first-set (paper's "-NoShift") */
+#define SMMO_TUNE_NO_COALESCE 2u    /* one slot per reservation ("-NoCoal") */
+#define SMMO_TUNE_STATS 4u          /* maintain device counters */
+#define SMMO_TUNE_FORCE_FAIL 8u     /* try_find_set fails force_fail_ppm / 1e6 of the time */
+
+/* -------------------------------------------------- heap management ---- */
+
+/* Bytes of device memory a heap of `num_blocks` blocks for these classes
+ * needs (metadata + scratch + data).  Classes: 1..SMMO_MAX_CLASSES, each with
+ * 1..SMMO_MAX_FIELDS fields; no class may be more than 64x the smallest
+ * (Sec. 3.2).  num_blocks: 1..2^36.  Errors: SMMO_EINVAL. */
+int smmo_heap_bytes(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks,
+                    uint64_t* bytes_out);
+
+/* Create a heap of `num_blocks` equal blocks (Sec. 3) inside the caller's
+ * device buffer `dev_mem` (256-B aligned, `dev_bytes` >= smmo_heap_bytes()).
+ * Enqueues the initialization on `stream`: every block free, every allocation
+ * word all ones ("invalidated", so a stale pick fails), bitmaps consistent.
+ * The caller keeps ownership of dev_mem and must keep it alive until
+ * smmo_heap_destroy.  Errors: SMMO_EINVAL, SMMO_ETOOSMALL, SMMO_EHIP. */
+int smmo_heap_create(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks,
+                     void* dev_mem, uint64_t dev_bytes, void* stream, smmo_heap** out);
+
+/* Free the host handle (never the device buffer).  NULL is accepted. */
+int smmo_heap_destroy(smmo_heap* heap);
+
+/* Re-initialize the heap to the empty state (all objects dropped). */
+int smmo_heap_reset(smmo_heap* heap, void* stream);
+
+/* Layout of class `cls` (host-side, no device access). */
+int smmo_class_layout(const smmo_heap* heap, uint32_t cls, smmo_layout* out);
+
+/* Tuning: flags SMMO_TUNE_*, lookups = active-block lookup attempts before
+ * the slow path (paper default 5; 1..64), force_fail_ppm for SMMO_TUNE_FORCE_FAIL.
+ * Enqueued on `stream`. */
+int smmo_set_tuning(smmo_heap* heap, uint32_t flags, uint32_t lookups, uint32_t force_fail_ppm,
+                    void* stream);
+
+/* ----------------------------------------------------- constructors ---- */
+/* ctor_id values.  A constructor runs on each new object right after its slot
+ * is reserved; `i` is the object's index in the creating call (Sec. 2.1:
+ * parallel_new passes 0..n-1). */
+#define SMMO_CTOR_ZERO 0u           /* all fields zero; args unused */
+#define SMMO_CTOR_ARRAYS 1u         /* fields from device arrays, see below */
+
+/* Argument blob of SMMO_CTOR_ARRAYS: field f of object i = src[f][i] (src[f]
+ * NULL: zero).  If ref_out is non-NULL the new handle is stored at
+ * ref_out[ref_index ? ref_index[i] : i].  All pointers are device pointers. */
+typedef struct smmo_ctor_arrays {
+    const void* src[SMMO_MAX_FIELDS];
+    uint64_t* ref_out;
+    const int32_t* ref_index;
+} smmo_ctor_arrays;
+
+/* ---------------------------------------------------------- methods ---- */
+/* method_id values for smmo_parallel_do.  A method runs once on every object
+ * of the class that is live when the do-all starts (Sec. 2.1, Sec. 3.1);
+ * objects it creates are not visited by the same do-all; it may destroy
+ * `this` and objects of other classes only. */
+#define SMMO_M_AXPY 0u              /* f32 fields: y += a*x           (smmo_axpy_args)  */
+#define SMMO_M_DESTROY_ALL 1u       /* every object destroys itself   (no args)         */
+#define SMMO_M_VISIT 2u             /* visits[id field 0] += 1        (smmo_visit_args) */
+#define SMMO_M_CHURN 3u             /* alloc microbench round         (smmo_churn_args) */
+#define SMMO_M_LIFE_PLAN 10u        /* Cell: next state, B3/S23       (smmo_life_args)  */
+#define SMMO_M_LIFE_AGENT 11u       /* Agent: die or age              (smmo_life_args)  */
+#define SMMO_M_LIFE_COMMIT 12u      /* Cell: birth of agents, commit  (smmo_life_args)  */
+#define SMMO_M_WATOR_FISH_PLAN 20u  /* Fish: age, choose and claim    (smmo_wator_args) */
+#define SMMO_M_WATOR_FISH_MOVE 21u  /* Fish: move, breed              (smmo_wator_args) */
+#define SMMO_M_WATOR_SHARK_PLAN 22u /* Shark: age, choose and claim   (smmo_wator_args) */
+#define SMMO_M_WATOR_SHARK_MOVE 23u /* Shark: move, eat, breed, starve(smmo_wator_args) */
+
+/* y += a*x on float32 fields fx, fy of the class (one rounding: a*x is formed
+ * first, then added). */
+typedef struct smmo_axpy_args { float a; uint32_t fx; uint32_t fy; uint32_t pad; } smmo_axpy_args;
+
+/* Test method: atomically increments visits[field0 (int32)]. */
+typedef struct smmo_visit_args { uint32_t* visits; } smmo_visit_args;
+
+/* Alloc microbench round `round` on class {int32 id, f32 x, f32 v}: each
+ * object with splitmix64(seed ^ id ^ round) odd destroys itself and allocates
+ * a replacement id' = ((round+1) << 18) | (id & 0x3FFFF) with
+ * x' = U01(ctr(seed, round+1, id', 0)), v' = U01(ctr(seed, round+1, id', 1)). */
+typedef struct smmo_churn_args { uint64_t seed; uint32_t round; uint32_t pad; } smmo_churn_args;
+
+/* Life-like grid on a width x height torus.  Cell {int32 x, int32 y, int8
+ * alive}: alive bit 0 = current, bit 1 = next.  Agent {int32 cell, int32 age}.
+ * cell_ref[c] is the handle of cell c = y*width + x (device array). */
+typedef struct smmo_life_args {
+    const uint64_t* cell_ref;
+    int32_t width, height;
+    uint32_t cell_cls, agent_cls;
+} smmo_life_args;
+
+/* Predator-prey grid on a width x height torus.  Fish {int32 pos, int32 age},
+ * Shark {int32 pos, int32 age, int32 energy}.  occ[c] is the handle on cell c
+ * (0 = empty); claim[c] must be INT32_MAX before a plan phase and is restored
+ * by the matching move phase; want[c] is scratch.  step is 1-based. */
+typedef struct smmo_wator_args {
+    uint64_t* occ;
+    int32_t* claim;
+    int32_t* want;
+    uint64_t seed;
+    int32_t width, height;
+    int32_t step;
+    int32_t fish_breed, shark_breed, eat_gain, shark_e0;
+    uint32_t fish_cls, shark_cls;
+    uint32_t pad;
+} smmo_wator_args;
+
+/* -------------------------------------------------------- operations ---- */
+
+/* parallel_new<T>(n) (Sec. 2.1): create n objects of class `cls`; object i
+ * gets constructor index i.  Placement: the lowest free blocks in ascending
+ * order, filled densely (object i at block rank i / N_T, slot i mod N_T).
+ * Sets SMMO_STATUS_OOM (and creates nothing) if too few blocks are free.
+ * args: the constructor's blob (copied; <= SMMO_ARGS_MAX bytes). */
+int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_id,
+                      const void* args, uint64_t args_bytes, void* stream);
+
+/* Device-side allocation from a kernel of `nthreads` threads, each calling
+ * new(d_allocator) T `per_thread` times in sequence (Sec. 2.1 "new"; the
+ * allocation microbenchmarks of Sec. 6.4).  Object of thread t, call k gets
+ * constructor index t*per_thread + k.  Allocation uses Alg. 1 with request
+ * coalescing per wavefront (Sec. 4.2). */
+int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32_t per_thread,
+                        uint32_t ctor_id, const void* args, uint64_t args_bytes, void* stream);
+
+/* parallel_do<T, method> (Sec. 2.1, Sec. 3.7): run `method_id` on every live
+ * object of class `cls`.  args: the method's blob (<= SMMO_ARGS_MAX bytes). */
+int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
+                     uint64_t args_bytes, void* stream);
+
+/* Live objects of class `cls`.  Synchronizes the stream. */
+int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream);
+
+/* Copy every live object of `cls` to host SOA arrays (host_field_bufs[f] has
+ * room for `cap` values of field f), in block order then slot order; *n_out
+ * = number of live objects (copying stops at cap).  Synchronizes. */
+int smmo_dump_objects(smmo_heap* heap, uint32_t cls, void* const* host_field_bufs, uint64_t cap,
+                      uint64_t* n_out, void* stream);
+
+/* Handles of every live object of `cls`, in the same order as
+ * smmo_dump_objects, to host memory.  Synchronizes. */
+int smmo_dump_refs(smmo_heap* heap, uint32_t cls, uint64_t* host_refs, uint64_t cap,
+                   uint64_t* n_out, void* stream);
+
+/* Bytes of the raw metadata region (header, status, block words, bitmaps). */
+int smmo_raw_bytes(const smmo_heap* heap, uint64_t* out);
+
+/* Copy the raw metadata region (smmo_raw_header first) to host_buf
+ * (`bytes` >= smmo_raw_bytes).  Synchronizes. */
+int smmo_dump_raw(smmo_heap* heap, void* host_buf, uint64_t bytes, void* stream);
+
+/* Sticky SMMO_STATUS_* bits.  Synchronizes. */
+int smmo_status(smmo_heap* heap, uint32_t* flags_out, void* stream);
+
+/* Clear the status bits and the counters. */
+int smmo_clear_status(smmo_heap* heap, void* stream);
+
+/* Copy `n` (<= SMMO_CNT_NUM) device counters to host.  Synchronizes. */
+int smmo_stats(smmo_heap* heap, uint64_t* out, uint32_t n, void* stream);
+
+/* Handle layout: bits 56-63 class id + 1, bits 6-49 block, bits 0-5 slot;
+ * 0 is the null handle.  Host-side helpers. */
+uint64_t smmo_ref_make(uint32_t cls, uint64_t block, uint32_t slot);
+uint32_t smmo_ref_class(uint64_t ref);
+uint64_t smmo_ref_block(uint64_t ref);
+uint32_t smmo_ref_slot(uint64_t ref);
+
+const char* smmo_strerror(int code);
+const char* smmo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMMO_H */

@@ -1,0 +1,41 @@
+"""Block capacity and SOA layout (test infrastructure only).
+
+Sec. 3.2: with s the smallest class, N_T = floor(64 * size(T_s) / size(T));
+a block of the smallest class holds 64 objects; a class more than 64 times
+bigger than the smallest cannot be stored.  size(T) is the sum of its field
+sizes: only SOA arrays are aligned, not objects (Sec. 6.2).  Each SOA array
+starts on a 128-byte boundary (the vector / cache-line granule of Sec. 2.3),
+arrays follow the declaration order, and every block has the byte size of the
+largest class layout so that all blocks are alike (Sec. 3).
+"""
+from __future__ import annotations
+
+
+def align(v: int, a: int) -> int:
+    return (v + a - 1) // a * a
+
+
+def capacity(classes, t: int) -> int:
+    sizes = [sum(c) for c in classes]
+    n = (64 * min(sizes)) // sizes[t]
+    if n < 1:
+        raise ValueError("class more than 64x bigger than the smallest class")
+    return n
+
+
+def layout(classes, align_bytes: int = 128):
+    """classes: list of lists of field byte sizes.
+
+    Returns (block_bytes, [(capacity, [field offsets])...]).
+    """
+    out = []
+    block = 0
+    for t, fields in enumerate(classes):
+        n = capacity(classes, t)
+        offs, cur = [], 0
+        for f in fields:
+            offs.append(cur)
+            cur += align(n * f, align_bytes)
+        out.append((n, offs))
+        block = max(block, cur)
+    return block, out
