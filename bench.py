@@ -1,0 +1,225 @@
+"""Benchmark of the SMMO hot path on one MI355X.
+
+Workload (the headline config): Life-like grid, 512 x 512 torus, Cell
+{int32 x, int32 y, int8 alive} objects and Agent {int32 cell, int32 age}
+objects created on birth and destroyed on death (B3/S23), initial density 0.3,
+16,384-block heap.  One step = the three do-alls of the workload
+(Cell::plan, Agent::step with destruction, Cell::commit with allocation),
+each enumerating its class from the block bitmaps.  The timed region is steps
+1..K of a freshly populated grid; the warm-up runs W steps on a separate
+grid first.
+
+Printed: one JSON line.  value = steps/s; roofline = the dominant kernel's
+algorithmic bytes per launch over its event-timed duration; cpu_baseline =
+the CPU oracle on the host.  Two sub-measurements of the same hot path are
+attached: the alloc microbench (alloc+destroy Mobj/s) and the do-all sweep at
+a heap six times the size of the Infinity Cache (GB/s vs HBM peak).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "alloc+destroy Mobj/s; parallel_do GB/s (% HBM peak); app steps/s plain vs batched"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-sub", action="store_true", help="skip the alloc / sweep sub-measurements")
+    p.add_argument("--sweep-blocks", type=int, default=1 << 21)
+    return p.parse_args()
+
+
+class Timer:
+    """HIP events on torch's current stream, which is the stream every
+    library call of this benchmark is queued on."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.spans = {}
+
+    def run(self, name, fn):
+        t = self.torch
+        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        self.spans.setdefault(name, []).append((a, b))
+
+    def ms(self, name):
+        return [a.elapsed_time(b) for a, b in self.spans.get(name, [])]
+
+
+def life_bench(torch, workloads, steps, warmup):
+    from paper_1810_11765_amd import smmo as S
+    if warmup:
+        g0 = workloads.LifeGrid(seed=42)
+        g0.populate()
+        for _ in range(warmup):
+            g0.step()
+        torch.cuda.synchronize()
+        del g0
+    g = workloads.LifeGrid(seed=42)
+    g.populate()
+    torch.cuda.synchronize()
+    # timed region: K whole steps, nothing else queued
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    status = g.heap.status()
+    # per-kernel durations: the same K steps again from a fresh grid, each
+    # do-all bracketed by events on the stream it is launched on
+    g2 = workloads.LifeGrid(seed=42)
+    g2.populate()
+    tm = Timer(torch)
+    for _ in range(steps):
+        tm.run("plan", lambda: g2.heap.parallel_do(g2.CELL, S.M_LIFE_PLAN, g2.args))
+        tm.run("agent", lambda: g2.heap.parallel_do(g2.AGENT, S.M_LIFE_AGENT, g2.args))
+        tm.run("commit", lambda: g2.heap.parallel_do(g2.CELL, S.M_LIFE_COMMIT, g2.args))
+    torch.cuda.synchronize()
+    per = {k: sum(tm.ms(k)) / steps for k in ("plan", "agent", "commit")}
+    return ms_step, per, status, g
+
+
+def roofline_for(per_ms):
+    """Dominant kernel of the step and its algorithmic-bytes roofline.
+
+    Algorithmic bytes per launch (unique data a launch must move at least):
+      plan   per cell: x, y (8) + alive read (1) + alive write (1) + its entry of
+             the cell -> handle table (8, read by its 8 neighbours) = 18 B
+      commit per cell: x, y (8) + alive read/write (2) = 10 B (+ 8 B per birth)
+      agent  per agent: cell, age (8) + age write (4) + table entry (8) + alive (1)
+    The plan kernel dominates; its launch processes all 262,144 cells.
+    """
+    name = max(per_ms, key=per_ms.get)
+    cells = 512 * 512
+    bytes_per = {"plan": 18.0 * cells, "commit": 10.0 * cells, "agent": 21.0 * cells * 0.3}
+    ms = per_ms[name]
+    achieved = bytes_per[name] / (ms * 1e-3) / 1e9
+    return name, {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                  "kernel": f"k_doall<{ {'plan': 'MLifePlan', 'agent': 'MLifeAgent', 'commit': 'MLifeCommit'}[name]}>",
+                  "ms_per_launch": round(ms, 5), "bytes_per_launch": int(bytes_per[name])}
+
+
+def alloc_sub(torch, workloads):
+    """Alloc microbench at its stated size: 65,536 threads x 4 device
+    allocations, then churn rounds (each ~131k destroys + ~131k allocs)."""
+    from paper_1810_11765_amd import smmo as S
+    wl = workloads.AllocBench(seed=42)
+    tm = Timer(torch)
+    tm.run("alloc", wl.initial_alloc)
+    for r in range(10):
+        wl.sweep()
+        tm.run("churn", lambda: wl.churn(r))
+    torch.cuda.synchronize()
+    # object counts of the same (deterministic) run, from the device counters
+    # of a second run with counting switched on (counting adds atomics, so it
+    # stays out of the timed run)
+    wl2 = workloads.AllocBench(seed=42)
+    wl2.heap.set_tuning(S.TUNE_STATS, 5, 0)
+    wl2.initial_alloc()
+    for r in range(10):
+        wl2.round(r)
+    st = wl2.heap.stats()
+    churn_objs = (st["alloc_obj"] - 262144) + st["free_obj"]
+    alloc_ms = tm.ms("alloc")[0]
+    churn_ms = sum(tm.ms("churn"))
+    return {"initial_alloc_mobj_s": round(262144 / (alloc_ms * 1e-3) / 1e6, 2),
+            "churn_alloc_destroy_mobj_s": round(churn_objs / (churn_ms * 1e-3) / 1e6, 2),
+            "churn_ms_per_round": round(churn_ms / 10, 4), "objects_per_round": churn_objs // 10,
+            "status": wl.heap.status()}
+
+
+def sweep_sub(torch, nblocks):
+    """parallel_do sweep v += 0.5*x over nblocks x 64 objects of 12 B."""
+    from paper_1810_11765_amd import smmo as S
+    h = S.Heap([[4, 4, 4]], nblocks)
+    n = nblocks * 64
+    h.parallel_new(0, n, S.CTOR_ZERO)
+    args = S.AxpyArgs(0.5, 1, 2, 0)
+    for _ in range(3):
+        h.parallel_do(0, S.M_AXPY, args)
+    tm = Timer(torch)
+    for _ in range(20):
+        tm.run("sweep", lambda: h.parallel_do(0, S.M_AXPY, args))
+    torch.cuda.synchronize()
+    ms = sorted(tm.ms("sweep"))[len(tm.ms("sweep")) // 2]
+    gbs = 12.0 * n / (ms * 1e-3) / 1e9
+    return {"objects": n, "bytes_per_sweep": 12 * n, "ms_median": round(ms, 4), "gbs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "status": h.status()}
+
+
+def cpu_baseline():
+    """The CPU oracle's Life run (single thread) on whole 200-step runs of the
+    same 512 x 512 workload, repeated until about 10 s of CPU time."""
+    from oracle import core
+    from paper_1810_11765_amd import inputs
+    a0 = inputs.life_initial(42, 512, 512)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 10.0:
+        core.c2_run(a0, 512, 512, 200)
+        steps += 200
+    dt = time.perf_counter() - t0
+    return {"value": round(steps / dt, 2), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps // 200} full runs of 200 steps of the 512x512 Life-like grid"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    from paper_1810_11765_amd import smmo, workloads
+    smmo.lib()                                   # fail loudly if the library is missing
+    ms_step, per, status, g = life_bench(torch, workloads, args.steps, args.warmup)
+    kname, roof = roofline_for(per)
+    out = {
+        "metric": METRIC,
+        "value": round(1e3 / ms_step, 2),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "life-like grid 512x512 torus, density 0.3, 200 steps, 16384-block heap, "
+                               "Cell{i32,i32,i8} + Agent{i32,i32}", "seed": 42, "mode": "plain"},
+        "kernel_ms_per_step": {k: round(v, 5) for k, v in per.items()},
+        "roofline": roof,
+        "device_status": status,
+    }
+    if not args.no_sub:
+        out["alloc_microbench"] = alloc_sub(torch, workloads)
+        out["sweep"] = sweep_sub(torch, args.sweep_blocks)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,10 @@ int smmo_heap_reset(smmo_heap* heap, void* stream);
 /* Layout of class `cls` (host-side, no device access). */
 int smmo_class_layout(const smmo_heap* heap, uint32_t cls, smmo_layout* out);
 
+/* Same layout computed from the class descriptors alone, without a heap
+ * (host-side only).  Errors: SMMO_EINVAL. */
+int smmo_layout_compute(const smmo_class_desc* cls, uint32_t ncls, uint32_t which, smmo_layout* out);
+
 /* Tuning: flags SMMO_TUNE_*, lookups = active-block lookup attempts before
  * the slow path (paper default 5; 1..64), force_fail_ppm for SMMO_TUNE_FORCE_FAIL.
  * Enqueued on `stream`. */
@@ -188,6 +192,7 @@ typedef struct smmo_ctor_arrays {
 #define SMMO_M_DESTROY_ALL 1u       /* every object destroys itself   (no args)         */
 #define SMMO_M_VISIT 2u             /* visits[id field 0] += 1        (smmo_visit_args) */
 #define SMMO_M_CHURN 3u             /* alloc microbench round         (smmo_churn_args) */
+#define SMMO_M_MIX 4u               /* two-class churn (test method)  (smmo_mix_args)   */
 #define SMMO_M_LIFE_PLAN 10u        /* Cell: next state, B3/S23       (smmo_life_args)  */
 #define SMMO_M_LIFE_AGENT 11u       /* Agent: die or age              (smmo_life_args)  */
 #define SMMO_M_LIFE_COMMIT 12u      /* Cell: birth of agents, commit  (smmo_life_args)  */
@@ -208,6 +213,18 @@ typedef struct smmo_visit_args { uint32_t* visits; } smmo_visit_args;
  * a replacement id' = ((round+1) << 18) | (id & 0x3FFFF) with
  * x' = U01(ctr(seed, round+1, id', 0)), v' = U01(ctr(seed, round+1, id', 1)). */
 typedef struct smmo_churn_args { uint64_t seed; uint32_t round; uint32_t pad; } smmo_churn_args;
+
+/* Two-class churn on classes whose field 0 is an int32 id (test method that
+ * makes blocks change type while other waves allocate): with
+ * h = splitmix64(seed ^ id ^ (round << 32)), an object with h odd destroys
+ * itself and allocates a replacement id' = ((round+1) << 18) | (id & 0x3FFFF)
+ * in class cls_b if bit 1 of h is set, else in cls_a.  Other fields: zero. */
+typedef struct smmo_mix_args {
+    uint64_t seed;
+    uint32_t round;
+    uint32_t cls_a, cls_b;
+    uint32_t pad;
+} smmo_mix_args;
 
 /* Life-like grid on a width x height torus.  Cell {int32 x, int32 y, int8
  * alive}: alive bit 0 = current, bit 1 = next.  Agent {int32 cell, int32 age}.

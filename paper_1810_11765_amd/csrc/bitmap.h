@@ -1,0 +1,109 @@
+// Lock-free hierarchical bitmap (DynaSOAr Sec. 4.1, Alg. 3 and 4, App. A.5).
+//
+// A bitmap of M bits is ceil(M/64) 64-bit containers plus, if that is more
+// than one word, a nested bitmap whose bit i is the OR of container i.  Every
+// level is eventually consistent with the one below: the operation that sets
+// the first bit or clears the last bit of a container is responsible for the
+// parent bit and updates it with the spinning (non-try) form (Sec. 4.1.3).
+//
+// On gfx950 these functions are executed by ONE lane of a wave (the wave's
+// leader); a spin here never waits on another lane of its own wave, which a
+// wave64 could not schedule (lanes of a wave share one program counter).
+// Every spin is bounded: past kSpinLimit it raises SMMO_STATUS_RETRY and gives
+// up, so a kernel always terminates even on a corrupted heap.
+#pragma once
+
+#include "dev.h"
+
+namespace smmo {
+
+constexpr uint32_t kSpinLimit = 1u << 16;
+
+__device__ inline uint64_t* bm_word(const DevHeap& h, uint32_t b, uint32_t level, uint64_t idx) {
+    return h.bm + (uint64_t)b * h.bitmap_words + h.level_off[level] + idx;
+}
+
+// set(pos) from `level` upwards: switch the bit 0 -> 1, retrying while it is
+// still 1 (a pending clear of another wave); a set-first continues one level up.
+__device__ inline void bm_set_from(const DevHeap& h, uint32_t b, uint32_t level, uint64_t pos) {
+    for (uint32_t l = level; l < h.nlevels; ++l) {
+        uint64_t* w = bm_word(h, b, l, pos >> 6);
+        const uint64_t bit = 1ull << (pos & 63);
+        uint64_t prev = at_or(w, bit);
+        uint32_t spins = 0;
+        while (prev & bit) {
+            if (++spins > kSpinLimit) { set_status(h, SMMO_STATUS_RETRY); return; }
+            count(h, SMMO_CNT_SPIN);
+            backoff();
+            prev = at_or(w, bit);
+        }
+        if (prev != 0) return;          // not the first bit of the container
+        pos >>= 6;
+    }
+}
+
+// clear(pos) from `level` upwards (spinning form).
+__device__ inline void bm_clear_from(const DevHeap& h, uint32_t b, uint32_t level, uint64_t pos) {
+    for (uint32_t l = level; l < h.nlevels; ++l) {
+        uint64_t* w = bm_word(h, b, l, pos >> 6);
+        const uint64_t bit = 1ull << (pos & 63);
+        uint64_t prev = at_and(w, ~bit);
+        uint32_t spins = 0;
+        while (!(prev & bit)) {
+            if (++spins > kSpinLimit) { set_status(h, SMMO_STATUS_RETRY); return; }
+            count(h, SMMO_CNT_SPIN);
+            backoff();
+            prev = at_and(w, ~bit);
+        }
+        if (prev != bit) return;        // container still has other bits (popc(prev) > 1)
+        pos >>= 6;
+    }
+}
+
+__device__ inline void bm_set(const DevHeap& h, uint32_t b, uint64_t pos) { bm_set_from(h, b, 0, pos); }
+__device__ inline void bm_clear(const DevHeap& h, uint32_t b, uint64_t pos) { bm_clear_from(h, b, 0, pos); }
+
+// try_clear(pos) (Alg. 3): one atomic AND; true if this call cleared the bit.
+__device__ inline bool bm_try_clear(const DevHeap& h, uint32_t b, uint64_t pos) {
+    uint64_t* w = bm_word(h, b, 0, pos >> 6);
+    const uint64_t bit = 1ull << (pos & 63);
+    uint64_t prev = at_and(w, ~bit);
+    if (!(prev & bit)) return false;
+    if (prev == bit && h.nlevels > 1) bm_clear_from(h, b, 1, pos >> 6);
+    return true;
+}
+
+// Rotated find-first-set: first set bit at or after position `rot`, cyclically
+// (Sec. 4.2 "Bitmap Rotation").
+__device__ inline uint32_t rot_ffs(uint64_t w, uint32_t rot) {
+    return (ctz64(rotr64(w, rot)) + rot) & 63;
+}
+
+// try_find_set() (Alg. 4), top-down from the single top word.  `seed` gives a
+// different rotation per level; it depends on the wave and changes per retry.
+__device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_t seed) {
+    if ((h.tune & SMMO_TUNE_FORCE_FAIL) && (uint32_t)(splitmix64(seed) % 1000000u) < h.force_fail_ppm)
+        return kFail;
+    const bool rotate = !(h.tune & SMMO_TUNE_NO_ROTATE);
+    uint64_t idx = 0;
+    for (int l = (int)h.nlevels - 1; l >= 0; --l) {
+        uint64_t w = at_load(bm_word(h, b, (uint32_t)l, idx));
+        if (!w) return kFail;
+        uint32_t bit = rotate ? rot_ffs(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
+        idx = (idx << 6) | bit;
+    }
+    return idx;
+}
+
+// clear(): find and clear any set bit; kFail if a lookup finds none.
+__device__ inline uint64_t bm_clear_any(const DevHeap& h, uint32_t b, uint64_t& seed) {
+    for (uint32_t tries = 0; tries < 64; ++tries) {
+        seed = splitmix64(seed);
+        uint64_t i = bm_try_find_set(h, b, seed);
+        if (i == kFail) return kFail;
+        if (bm_try_clear(h, b, i)) return i;
+    }
+    return kFail;
+}
+
+}  // namespace smmo

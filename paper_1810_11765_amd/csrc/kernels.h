@@ -1,0 +1,255 @@
+// Kernels of the SMMO heap: heap initialization, iteration snapshot,
+// parallel do-all, parallel_new, device-side allocation, live counting.
+#pragma once
+
+#include "alloc.h"
+
+namespace smmo {
+
+constexpr uint32_t kBlockThreads = 256;   // 4 waves per workgroup
+
+__device__ inline uint64_t global_wave() {
+    return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+}
+__device__ inline uint64_t wave_seed(uint64_t a, uint64_t b) {
+    return splitmix64((a << 24) ^ b ^ 0x5deece66dull);
+}
+
+// ------------------------------------------------------------------ init ----
+// Per-block words: type none, allocation word all ones (Q: a never-used block
+// looks invalidated, so a stale pick fails), iteration word 0.
+__global__ void k_init_blocks(DevHeap h) {
+    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= h.M) return;
+    h.type[b] = kNoType;
+    h.alloc[b] = kOnes;
+    h.iter[b] = 0;
+}
+
+// Bitmap words: free = all M bits set (every level consistent), allocated[*]
+// and active[*] empty.  One thread per word of the bitmap area.
+__global__ void k_init_bitmaps(DevHeap h, uint64_t nwords_total) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nwords_total) return;
+    uint64_t b = i / h.bitmap_words, off = i % h.bitmap_words;
+    uint64_t v = 0;
+    if (b == bm_free()) {
+        uint64_t nbits = h.M;
+#pragma unroll
+        for (uint32_t l = 0; l < SMMO_MAX_LEVELS; ++l) {
+            if (l < h.nlevels && off >= h.level_off[l] && off < h.level_off[l] + h.level_words[l]) {
+                uint64_t k = off - h.level_off[l];
+                uint64_t lo = k * 64;
+                v = nbits >= lo + 64 ? kOnes : (nbits > lo ? ((1ull << (nbits - lo)) - 1) : 0);
+            }
+            nbits = h.level_words[l];
+        }
+    }
+    h.bm[i] = v;
+    if (i == 0) {
+        *h.status = 0;
+        for (int c = 0; c < SMMO_CNT_NUM; ++c) h.counters[c] = 0;
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n, uint64_t v) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// --------------------------------------------------- iteration snapshot ----
+// iter <- alloc (without padding) for every allocated block of `cls`, before
+// a do-all whose method may create objects of its own class (Sec. 3.1).
+__global__ void k_snapshot(DevHeap h, uint32_t cls) {
+    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= h.M) return;
+    uint64_t w = *bm_word(h, bm_allocated(cls), 0, b >> 6);
+    if ((w >> (b & 63)) & 1) h.iter[b] = h.alloc[b] & ~h.cls_pad[cls];
+}
+
+// ----------------------------------------------------------- do-all ----
+// Per-lane view of the object in (block, slot = lane).
+struct Obj {
+    const DevHeap& h;
+    uint32_t cls;
+    uint64_t bid;
+    uint32_t lane;
+    bool live;          // slot enumerated by this do-all
+    uint8_t* base;      // block data segment
+    uint64_t seed;      // per-wave seed for allocator rotations
+    template <class F>
+    __device__ F& at(uint32_t off) const { return *reinterpret_cast<F*>(base + off + lane * sizeof(F)); }
+    __device__ uint64_t self() const { return make_ref(cls, bid, lane); }
+};
+
+// Parallel do-all (Sec. 3.7), enumeration fused in: the L0 words of
+// allocated[cls] are cut into units of 64 >> s_log2 block bits; a wave takes a
+// unit (grid-stride), walks its set bits in ascending order (the bitmap scan
+// is the compaction) and runs the method on each block with lane = slot, so
+// every field access of the wave is one contiguous SOA segment.  Objects the
+// method creates are not visited: with M::kSnapshot the wave reads the
+// iteration word written by k_snapshot (blocks initialized meanwhile have it
+// zeroed), otherwise no object of the class can appear during the do-all and
+// the allocation word itself is the snapshot.
+template <class M>
+__global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls, uint32_t s_log2,
+                                                          uint64_t nunits, typename M::Args a) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = global_wave();
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t* l0 = bm_word(h, bm_allocated(cls), 0, 0);
+    const uint64_t valid = ~h.cls_pad[cls];
+    const uint32_t span = 64u >> s_log2;
+    const uint64_t span_mask = span == 64 ? kOnes : ((1ull << span) - 1);
+    const typename M::Prep prep = M::prepare(h, cls, a);
+    for (uint64_t u = wave; u < nunits; u += nwaves) {
+        const uint64_t w = u >> s_log2;
+        const uint32_t sub = (uint32_t)(u & ((1u << s_log2) - 1));
+        uint64_t word = at_load(l0 + w) & (span_mask << (sub * span));
+        while (word) {
+            const uint32_t b = ctz64(word);
+            word &= word - 1;
+            const uint64_t bid = (w << 6) | b;
+            const uint64_t live = (M::kSnapshot ? at_load(&h.iter[bid]) : at_load(&h.alloc[bid])) & valid;
+            Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
+                  wave_seed(wave, bid)};
+            M::run(o, prep, a);
+        }
+    }
+}
+
+// ------------------------------------------------------ parallel_new ----
+// Lowest `nb` free blocks in ascending order -> R[0..nb); *found = how many.
+// One workgroup; each thread scans a contiguous range of L0 words.
+__global__ __launch_bounds__(1024) void k_find_free(DevHeap h, uint64_t nb, uint32_t* R,
+                                                    unsigned long long* found) {
+    __shared__ unsigned long long wsum[16];
+    __shared__ unsigned long long total_s;
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint64_t W0 = (h.M + 63) >> 6;
+    const uint64_t per = (W0 + 1023) / 1024;
+    const uint64_t lo = (uint64_t)t * per, hi = lo + per < W0 ? lo + per : W0;
+    const uint64_t* l0 = bm_word(h, bm_free(), 0, 0);
+    unsigned long long cnt = 0;
+    for (uint64_t i = lo; i < hi; ++i) cnt += popc64(l0[i]);
+    // inclusive scan inside the wave
+    unsigned long long inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        unsigned long long y = __shfl_up(inc, o, 64);
+        if (lane >= (uint32_t)o) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long s = 0;
+        for (int i = 0; i < 16; ++i) { unsigned long long v = wsum[i]; wsum[i] = s; s += v; }
+        total_s = s;
+    }
+    __syncthreads();
+    unsigned long long off = wsum[wv] + inc - cnt;
+    for (uint64_t i = lo; i < hi && off < nb; ++i) {
+        uint64_t w = l0[i];
+        while (w && off < nb) {
+            R[off++] = (uint32_t)((i << 6) | ctz64(w));
+            w &= w - 1;
+        }
+    }
+    if (t == 0) *found = total_s < nb ? total_s : nb;
+}
+
+// Fill block rank j (one wave per block) with objects j*N .. j*N+cnt-1.
+template <class C>
+__global__ __launch_bounds__(kBlockThreads) void k_new_fill(DevHeap h, uint32_t cls, uint64_t n,
+                                                             const uint32_t* R, const unsigned long long* found,
+                                                             typename C::Args a) {
+    const uint32_t lane = lane_id();
+    const uint64_t j = global_wave();
+    const uint32_t N = h.cls_cap[cls];
+    const uint64_t nb = (n + N - 1) / N;
+    if (j >= nb) return;                                  // wave-uniform
+    if (*found < nb) {
+        if (j == 0 && lane == 0) set_status(h, SMMO_STATUS_OOM);
+        return;
+    }
+    const uint64_t bid = R[j];
+    const uint64_t rem = n - j * N;
+    const uint32_t cnt = rem < N ? (uint32_t)rem : N;
+    if (lane == 0) {
+        const uint64_t live = cnt == 64 ? kOnes : ((1ull << cnt) - 1);
+        at_store32(&h.type[bid], cls);
+        at_store(&h.iter[bid], 0);
+        at_store_rel(&h.alloc[bid], h.cls_pad[cls] | live);
+        bm_clear(h, bm_free(), bid);
+        bm_set(h, bm_allocated(cls), bid);
+        if (cnt < N) bm_set(h, bm_active(h, cls), bid);
+    }
+    if (lane < cnt) C::run(h, cls, bid, lane, j * N + lane, make_ref(cls, bid, lane), a);
+}
+
+// --------------------------------------------- device-side allocation ----
+// nthreads threads each allocate `per` objects in sequence; object of thread
+// t, call k gets constructor index t*per + k.
+template <class C>
+__global__ __launch_bounds__(kBlockThreads) void k_alloc(DevHeap h, uint32_t cls, uint64_t nthreads,
+                                                          uint32_t per, typename C::Args a) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t wave = global_wave();
+    if ((wave << 6) >= nthreads) return;                 // wave-uniform
+    const bool act = tid < nthreads;
+    for (uint32_t k = 0; k < per; ++k) {
+        uint64_t ref = wave_alloc(h, cls, act, wave_seed(wave, k));
+        if (act && ref) C::run(h, cls, ref_block(ref), ref_slot(ref), tid * per + k, ref, a);
+    }
+}
+
+// ------------------------------------------------------------ counting ----
+__global__ void k_live_count(DevHeap h, uint32_t cls, unsigned long long* out) {
+    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = 0;
+    if (b < h.M) {
+        uint64_t w = *bm_word(h, bm_allocated(cls), 0, b >> 6);
+        if ((w >> (b & 63)) & 1) c = popc64(h.alloc[b] & ~h.cls_pad[cls]);
+    }
+    c = wave_add(c);
+    if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+// -------------------------------------------------------- constructors ----
+struct CtorZero {
+    struct Args { uint64_t unused; };
+    __device__ static void run(const DevHeap& h, uint32_t cls, uint64_t bid, uint32_t slot, uint64_t,
+                               uint64_t, const Args&) {
+        const uint32_t nf = (uint32_t)h.hdr->nfields[cls];
+        for (uint32_t f = 0; f < nf; ++f) {
+            uint8_t* p = field_addr(h, cls, bid, slot, f);
+            switch (h.hdr->field_bytes[cls][f]) {
+                case 1: *p = 0; break;
+                case 2: *reinterpret_cast<uint16_t*>(p) = 0; break;
+                case 4: *reinterpret_cast<uint32_t*>(p) = 0; break;
+                default: *reinterpret_cast<uint64_t*>(p) = 0; break;
+            }
+        }
+    }
+};
+
+struct CtorArrays {
+    using Args = smmo_ctor_arrays;
+    __device__ static void run(const DevHeap& h, uint32_t cls, uint64_t bid, uint32_t slot, uint64_t i,
+                               uint64_t ref, const Args& a) {
+        const uint32_t nf = (uint32_t)h.hdr->nfields[cls];
+        for (uint32_t f = 0; f < nf; ++f) {
+            uint8_t* p = field_addr(h, cls, bid, slot, f);
+            const uint8_t* s = static_cast<const uint8_t*>(a.src[f]);
+            switch (h.hdr->field_bytes[cls][f]) {
+                case 1: *p = s ? s[i] : 0; break;
+                case 2: *reinterpret_cast<uint16_t*>(p) = s ? reinterpret_cast<const uint16_t*>(s)[i] : 0; break;
+                case 4: *reinterpret_cast<uint32_t*>(p) = s ? reinterpret_cast<const uint32_t*>(s)[i] : 0; break;
+                default: *reinterpret_cast<uint64_t*>(p) = s ? reinterpret_cast<const uint64_t*>(s)[i] : 0; break;
+            }
+        }
+        if (a.ref_out) a.ref_out[a.ref_index ? (uint64_t)a.ref_index[i] : i] = ref;
+    }
+};
+
+}  // namespace smmo

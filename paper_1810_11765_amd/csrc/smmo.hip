@@ -1,0 +1,535 @@
+// Host side of the SMMO heap C-ABI (include/smmo.h): heap layout, argument
+// checking, kernel dispatch.  Every compute step runs in the kernels of
+// kernels.h / methods.h; this file only lays out memory and launches them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "methods.h"
+
+using namespace smmo;
+
+struct smmo_heap {
+    smmo_raw_header hdr;   // host copy of the device header
+    DevHeap dev;           // kernel-argument view
+    uint8_t* base;         // caller's device buffer
+    uint64_t bytes;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(SMMO_EHIP, "%s: %s", #expr, hipGetErrorString(e_));           \
+    } while (0)
+
+#define LAUNCH_CHECK(name)                                                            \
+    do {                                                                              \
+        hipError_t e_ = hipGetLastError();                                            \
+        if (e_ != hipSuccess) return fail(SMMO_EHIP, "%s launch: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline unsigned grid_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+// Layout of every class (Sec. 3.2): N_T = floor(64 * size(T_s) / size(T));
+// SOA arrays in declaration order, each starting on a 128-B boundary; every
+// block has the size of the largest class layout.
+int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_raw_header* hdr) {
+    if (!cls || ncls == 0 || ncls > SMMO_MAX_CLASSES) return fail(SMMO_EINVAL, "ncls must be 1..%d", SMMO_MAX_CLASSES);
+    if (M == 0 || M > (1ull << 36)) return fail(SMMO_EINVAL, "num_blocks must be 1..2^36");
+    std::memset(hdr, 0, sizeof *hdr);
+    uint64_t size[SMMO_MAX_CLASSES];
+    uint64_t smin = ~0ull;
+    for (uint32_t t = 0; t < ncls; ++t) {
+        if (cls[t].nfields == 0 || cls[t].nfields > SMMO_MAX_FIELDS || !cls[t].field_bytes)
+            return fail(SMMO_EINVAL, "class %u: nfields must be 1..%d", t, SMMO_MAX_FIELDS);
+        size[t] = 0;
+        for (uint32_t f = 0; f < cls[t].nfields; ++f) {
+            uint32_t b = cls[t].field_bytes[f];
+            if (b != 1 && b != 2 && b != 4 && b != 8)
+                return fail(SMMO_EINVAL, "class %u field %u: size %u not 1/2/4/8", t, f, b);
+            size[t] += b;
+        }
+        smin = std::min(smin, size[t]);
+    }
+    uint64_t block = 0;
+    for (uint32_t t = 0; t < ncls; ++t) {
+        uint64_t n = 64 * smin / size[t];
+        if (n < 1) return fail(SMMO_EINVAL, "class %u is more than 64x the smallest class", t);
+        hdr->capacity[t] = n;
+        hdr->nfields[t] = cls[t].nfields;
+        uint64_t off = 0;
+        for (uint32_t f = 0; f < cls[t].nfields; ++f) {
+            hdr->field_bytes[t][f] = cls[t].field_bytes[f];
+            hdr->field_off[t][f] = (uint32_t)off;
+            off += align_up(n * cls[t].field_bytes[f], 128);
+        }
+        block = std::max(block, off);
+    }
+    hdr->magic = SMMO_MAGIC;
+    hdr->version = 1;
+    hdr->num_blocks = M;
+    hdr->ncls = ncls;
+    hdr->block_bytes = block;
+    // bitmap geometry: level 0 has one bit per block, each next level one bit
+    // per word of the level below, up to a single top word
+    uint64_t nbits = M, off = 0;
+    uint32_t l = 0;
+    for (;;) {
+        if (l >= SMMO_MAX_LEVELS) return fail(SMMO_EINVAL, "too many blocks for %d bitmap levels", SMMO_MAX_LEVELS);
+        uint64_t words = (nbits + 63) / 64;
+        hdr->level_words[l] = words;
+        hdr->level_off[l] = off;
+        off += align_up(words, 8);
+        ++l;
+        if (words == 1) break;
+        nbits = words;
+    }
+    hdr->nlevels = l;
+    hdr->bitmap_words = align_up(off, 32);
+    // sections of the device buffer
+    uint64_t p = 4096;                                     // header
+    hdr->off_status = p;       p += 256;
+    hdr->off_type = p;         p = align_up(p + 4 * M, 256);
+    hdr->off_alloc = p;        p = align_up(p + 8 * M, 256);
+    hdr->off_iter = p;         p = align_up(p + 8 * M, 256);
+    hdr->off_bitmaps = p;      p = align_up(p + 8 * hdr->bitmap_words * (1 + 2 * (uint64_t)ncls), 256);
+    hdr->off_scratch = p;
+    hdr->scratch_bytes = align_up(256 + 4 * M, 256);
+    p += hdr->scratch_bytes;
+    hdr->off_data = align_up(p, 4096);
+    hdr->total_bytes = hdr->off_data + M * block;
+    hdr->tune_flags = 0;
+    hdr->lookups = 5;                                      // Sec. 6.3: r = 5 by default
+    hdr->force_fail_ppm = 0;
+    return SMMO_OK;
+}
+
+void fill_dev(smmo_heap* H) {
+    const smmo_raw_header& h = H->hdr;
+    DevHeap& d = H->dev;
+    std::memset(&d, 0, sizeof d);
+    uint8_t* b = H->base;
+    d.data = b + h.off_data;
+    d.alloc = reinterpret_cast<uint64_t*>(b + h.off_alloc);
+    d.iter = reinterpret_cast<uint64_t*>(b + h.off_iter);
+    d.type = reinterpret_cast<uint32_t*>(b + h.off_type);
+    d.bm = reinterpret_cast<uint64_t*>(b + h.off_bitmaps);
+    d.status = reinterpret_cast<uint32_t*>(b + h.off_status);
+    d.counters = reinterpret_cast<unsigned long long*>(b + h.off_status + 64);
+    d.scratch = b + h.off_scratch;
+    d.hdr = reinterpret_cast<const smmo_raw_header*>(b);
+    d.M = h.num_blocks;
+    d.block_bytes = h.block_bytes;
+    d.bitmap_words = h.bitmap_words;
+    for (int l = 0; l < SMMO_MAX_LEVELS; ++l) {
+        d.level_off[l] = h.level_off[l];
+        d.level_words[l] = h.level_words[l];
+    }
+    d.nlevels = (uint32_t)h.nlevels;
+    d.ncls = (uint32_t)h.ncls;
+    d.tune = h.tune_flags;
+    d.lookups = h.lookups;
+    d.force_fail_ppm = h.force_fail_ppm;
+    for (uint32_t t = 0; t < h.ncls; ++t) {
+        uint64_t n = h.capacity[t];
+        d.cls_cap[t] = (uint32_t)n;
+        d.cls_pad[t] = n >= 64 ? 0ull : (~0ull << n);
+    }
+}
+
+int init_device(smmo_heap* H, hipStream_t s) {
+    const smmo_raw_header& h = H->hdr;
+    HIP_TRY(hipMemcpyAsync(H->base, &H->hdr, sizeof H->hdr, hipMemcpyHostToDevice, s));
+    k_init_blocks<<<grid_for(h.num_blocks, 256), 256, 0, s>>>(H->dev);
+    LAUNCH_CHECK("k_init_blocks");
+    uint64_t nw = h.bitmap_words * (1 + 2 * h.ncls);
+    k_init_bitmaps<<<grid_for(nw, 256), 256, 0, s>>>(H->dev, nw);
+    LAUNCH_CHECK("k_init_bitmaps");
+    HIP_TRY(hipStreamSynchronize(s));                      // the header copy reads host memory
+    return SMMO_OK;
+}
+
+unsigned long long* scratch_counter(smmo_heap* H, int i) {
+    return reinterpret_cast<unsigned long long*>(H->dev.scratch) + i;
+}
+uint32_t* scratch_R(smmo_heap* H) { return reinterpret_cast<uint32_t*>(H->dev.scratch + 256); }
+
+int check_heap_cls(const smmo_heap* H, uint32_t cls) {
+    if (!H) return fail(SMMO_EINVAL, "null heap");
+    if (cls >= H->hdr.ncls) return fail(SMMO_EINVAL, "class %u out of range (%llu classes)", cls,
+                                        (unsigned long long)H->hdr.ncls);
+    return SMMO_OK;
+}
+
+template <class A>
+int unpack_args(A& a, const void* args, uint64_t bytes, const char* what) {
+    std::memset(&a, 0, sizeof a);
+    if (bytes == 0 && args == nullptr) return SMMO_OK;
+    if (bytes != sizeof(A) || !args)
+        return fail(SMMO_EINVAL, "%s: argument blob of %llu bytes, expected %zu", what,
+                    (unsigned long long)bytes, sizeof(A));
+    std::memcpy(&a, args, sizeof a);
+    return SMMO_OK;
+}
+
+// units of 64 >> s_log2 block bits so that small heaps still spread over
+// enough waves; big heaps get whole words per unit and a capped grid
+void doall_geometry(const smmo_heap* H, uint32_t& s_log2, uint64_t& nunits, unsigned& grid) {
+    const uint64_t W0 = H->hdr.level_words[0];
+    const uint64_t target = 16384;                         // waves wanted in flight
+    s_log2 = 0;
+    while (s_log2 < 6 && (W0 << s_log2) < target) ++s_log2;
+    nunits = W0 << s_log2;
+    const uint64_t waves = std::min<uint64_t>(nunits, 256ull * 32);
+    grid = (unsigned)((waves + 3) / 4);
+}
+
+template <class M>
+int launch_doall(smmo_heap* H, uint32_t cls, const void* args, uint64_t bytes, hipStream_t s) {
+    typename M::Args a;
+    int rc = unpack_args(a, args, bytes, "parallel_do");
+    if (rc) return rc;
+    if (M::kSnapshot) {
+        k_snapshot<<<grid_for(H->hdr.num_blocks, 256), 256, 0, s>>>(H->dev, cls);
+        LAUNCH_CHECK("k_snapshot");
+    }
+    uint32_t s_log2;
+    uint64_t nunits;
+    unsigned grid;
+    doall_geometry(H, s_log2, nunits, grid);
+    k_doall<M><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, a);
+    LAUNCH_CHECK("k_doall");
+    return SMMO_OK;
+}
+
+template <class C>
+int launch_new(smmo_heap* H, uint32_t cls, uint64_t n, const void* args, uint64_t bytes, hipStream_t s) {
+    typename C::Args a;
+    int rc = unpack_args(a, args, bytes, "parallel_new");
+    if (rc) return rc;
+    const uint64_t N = H->hdr.capacity[cls];
+    const uint64_t nb = (n + N - 1) / N;
+    if (nb > H->hdr.num_blocks) return fail(SMMO_EINVAL, "parallel_new: %llu objects need %llu blocks, heap has %llu",
+                                            (unsigned long long)n, (unsigned long long)nb,
+                                            (unsigned long long)H->hdr.num_blocks);
+    k_find_free<<<1, 1024, 0, s>>>(H->dev, nb, scratch_R(H), scratch_counter(H, 0));
+    LAUNCH_CHECK("k_find_free");
+    k_new_fill<C><<<grid_for(nb * 64, kBlockThreads), kBlockThreads, 0, s>>>(H->dev, cls, n, scratch_R(H),
+                                                                              scratch_counter(H, 0), a);
+    LAUNCH_CHECK("k_new_fill");
+    return SMMO_OK;
+}
+
+template <class C>
+int launch_alloc(smmo_heap* H, uint32_t cls, uint64_t nthreads, uint32_t per, const void* args, uint64_t bytes,
+                 hipStream_t s) {
+    typename C::Args a;
+    int rc = unpack_args(a, args, bytes, "parallel_alloc");
+    if (rc) return rc;
+    k_alloc<C><<<grid_for(nthreads, kBlockThreads), kBlockThreads, 0, s>>>(H->dev, cls, nthreads, per, a);
+    LAUNCH_CHECK("k_alloc");
+    return SMMO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int smmo_heap_bytes(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks, uint64_t* bytes_out) {
+    smmo_raw_header h;
+    int rc = compute_layout(cls, ncls, num_blocks, &h);
+    if (rc) return rc;
+    if (!bytes_out) return fail(SMMO_EINVAL, "null bytes_out");
+    *bytes_out = h.total_bytes;
+    return SMMO_OK;
+}
+
+int smmo_heap_create(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks, void* dev_mem,
+                     uint64_t dev_bytes, void* stream, smmo_heap** out) {
+    if (!out || !dev_mem) return fail(SMMO_EINVAL, "null out or dev_mem");
+    if (reinterpret_cast<uintptr_t>(dev_mem) % 256) return fail(SMMO_EINVAL, "dev_mem must be 256-B aligned");
+    smmo_heap* H = new smmo_heap();
+    int rc = compute_layout(cls, ncls, num_blocks, &H->hdr);
+    if (rc) { delete H; return rc; }
+    if (dev_bytes < H->hdr.total_bytes) {
+        unsigned long long need = H->hdr.total_bytes;
+        delete H;
+        return fail(SMMO_ETOOSMALL, "dev_bytes %llu < required %llu", (unsigned long long)dev_bytes, need);
+    }
+    H->base = static_cast<uint8_t*>(dev_mem);
+    H->bytes = dev_bytes;
+    fill_dev(H);
+    rc = init_device(H, S(stream));
+    if (rc) { delete H; return rc; }
+    *out = H;
+    return SMMO_OK;
+}
+
+int smmo_heap_destroy(smmo_heap* heap) {
+    delete heap;
+    return SMMO_OK;
+}
+
+int smmo_heap_reset(smmo_heap* heap, void* stream) {
+    if (!heap) return fail(SMMO_EINVAL, "null heap");
+    return init_device(heap, S(stream));
+}
+
+int smmo_class_layout(const smmo_heap* heap, uint32_t cls, smmo_layout* out) {
+    int rc = check_heap_cls(heap, cls);
+    if (rc) return rc;
+    if (!out) return fail(SMMO_EINVAL, "null out");
+    std::memset(out, 0, sizeof *out);
+    out->capacity = (uint32_t)heap->hdr.capacity[cls];
+    out->nfields = (uint32_t)heap->hdr.nfields[cls];
+    out->block_bytes = heap->hdr.block_bytes;
+    for (uint32_t f = 0; f < out->nfields; ++f) {
+        out->field_bytes[f] = heap->hdr.field_bytes[cls][f];
+        out->field_offset[f] = heap->hdr.field_off[cls][f];
+    }
+    return SMMO_OK;
+}
+
+int smmo_layout_compute(const smmo_class_desc* cls, uint32_t ncls, uint32_t which, smmo_layout* out) {
+    smmo_heap tmp;
+    int rc = compute_layout(cls, ncls, 1, &tmp.hdr);
+    if (rc) return rc;
+    return smmo_class_layout(&tmp, which, out);
+}
+
+int smmo_set_tuning(smmo_heap* heap, uint32_t flags, uint32_t lookups, uint32_t force_fail_ppm, void* stream) {
+    if (!heap) return fail(SMMO_EINVAL, "null heap");
+    if (lookups < 1 || lookups > 64) return fail(SMMO_EINVAL, "lookups must be 1..64");
+    if (force_fail_ppm > 1000000) return fail(SMMO_EINVAL, "force_fail_ppm must be <= 1e6");
+    heap->hdr.tune_flags = flags;
+    heap->hdr.lookups = lookups;
+    heap->hdr.force_fail_ppm = force_fail_ppm;
+    heap->dev.tune = flags;
+    heap->dev.lookups = lookups;
+    heap->dev.force_fail_ppm = force_fail_ppm;
+    // keep the device header (dumped by smmo_dump_raw) in step
+    const size_t off = offsetof(smmo_raw_header, tune_flags);
+    HIP_TRY(hipMemcpyAsync(heap->base + off, reinterpret_cast<uint8_t*>(&heap->hdr) + off, 12,
+                           hipMemcpyHostToDevice, S(stream)));
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    return SMMO_OK;
+}
+
+int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_id, const void* args,
+                      uint64_t args_bytes, void* stream) {
+    int rc = check_heap_cls(heap, cls);
+    if (rc) return rc;
+    if (n == 0) return SMMO_OK;
+    switch (ctor_id) {
+        case SMMO_CTOR_ZERO: return launch_new<CtorZero>(heap, cls, n, args, args_bytes, S(stream));
+        case SMMO_CTOR_ARRAYS: return launch_new<CtorArrays>(heap, cls, n, args, args_bytes, S(stream));
+        default: return fail(SMMO_EINVAL, "unknown ctor_id %u", ctor_id);
+    }
+}
+
+int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32_t per_thread, uint32_t ctor_id,
+                        const void* args, uint64_t args_bytes, void* stream) {
+    int rc = check_heap_cls(heap, cls);
+    if (rc) return rc;
+    if (nthreads == 0 || per_thread == 0) return SMMO_OK;
+    switch (ctor_id) {
+        case SMMO_CTOR_ZERO:
+            return launch_alloc<CtorZero>(heap, cls, nthreads, per_thread, args, args_bytes, S(stream));
+        case SMMO_CTOR_ARRAYS:
+            return launch_alloc<CtorArrays>(heap, cls, nthreads, per_thread, args, args_bytes, S(stream));
+        default: return fail(SMMO_EINVAL, "unknown ctor_id %u", ctor_id);
+    }
+}
+
+int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args, uint64_t args_bytes,
+                     void* stream) {
+    int rc = check_heap_cls(heap, cls);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    switch (method_id) {
+        case SMMO_M_AXPY: {
+            smmo_axpy_args a;
+            rc = unpack_args(a, args, args_bytes, "axpy");
+            if (rc) return rc;
+            if (a.fx >= heap->hdr.nfields[cls] || a.fy >= heap->hdr.nfields[cls] ||
+                heap->hdr.field_bytes[cls][a.fx] != 4 || heap->hdr.field_bytes[cls][a.fy] != 4)
+                return fail(SMMO_EINVAL, "axpy: fields must be 4-byte fields of the class");
+            return launch_doall<MAxpy>(heap, cls, args, args_bytes, s);
+        }
+        case SMMO_M_DESTROY_ALL: return launch_doall<MDestroyAll>(heap, cls, nullptr, 0, s);
+        case SMMO_M_VISIT: return launch_doall<MVisit>(heap, cls, args, args_bytes, s);
+        case SMMO_M_CHURN: return launch_doall<MChurn>(heap, cls, args, args_bytes, s);
+        case SMMO_M_MIX: {
+            smmo_mix_args a;
+            rc = unpack_args(a, args, args_bytes, "mix");
+            if (rc) return rc;
+            if (a.cls_a >= heap->hdr.ncls || a.cls_b >= heap->hdr.ncls || heap->hdr.field_bytes[a.cls_a][0] != 4 ||
+                heap->hdr.field_bytes[a.cls_b][0] != 4 || heap->hdr.field_bytes[cls][0] != 4)
+                return fail(SMMO_EINVAL, "mix: classes need an int32 field 0");
+            return launch_doall<MMix>(heap, cls, args, args_bytes, s);
+        }
+        case SMMO_M_LIFE_PLAN: return launch_doall<MLifePlan>(heap, cls, args, args_bytes, s);
+        case SMMO_M_LIFE_AGENT: return launch_doall<MLifeAgent>(heap, cls, args, args_bytes, s);
+        case SMMO_M_LIFE_COMMIT: return launch_doall<MLifeCommit>(heap, cls, args, args_bytes, s);
+        case SMMO_M_WATOR_FISH_PLAN: return launch_doall<MFishPlan>(heap, cls, args, args_bytes, s);
+        case SMMO_M_WATOR_FISH_MOVE: return launch_doall<MFishMove>(heap, cls, args, args_bytes, s);
+        case SMMO_M_WATOR_SHARK_PLAN: return launch_doall<MSharkPlan>(heap, cls, args, args_bytes, s);
+        case SMMO_M_WATOR_SHARK_MOVE: return launch_doall<MSharkMove>(heap, cls, args, args_bytes, s);
+        default: return fail(SMMO_EINVAL, "unknown method_id %u", method_id);
+    }
+}
+
+int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream) {
+    int rc = check_heap_cls(heap, cls);
+    if (rc) return rc;
+    if (!out) return fail(SMMO_EINVAL, "null out");
+    hipStream_t s = S(stream);
+    unsigned long long* c = scratch_counter(heap, 1);
+    k_fill_u64<<<1, 64, 0, s>>>(c, 1, 0);
+    LAUNCH_CHECK("k_fill_u64");
+    k_live_count<<<grid_for(heap->hdr.num_blocks, 256), 256, 0, s>>>(heap->dev, cls, c);
+    LAUNCH_CHECK("k_live_count");
+    unsigned long long v = 0;
+    HIP_TRY(hipMemcpyAsync(&v, c, sizeof v, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = v;
+    return SMMO_OK;
+}
+
+// host-side walk over a copy of the metadata and data (introspection, not the
+// hot path)
+static int dump_walk(smmo_heap* heap, uint32_t cls, void* const* bufs, uint64_t* refs, uint64_t cap,
+                     uint64_t* n_out, void* stream) {
+    int rc = check_heap_cls(heap, cls);
+    if (rc) return rc;
+    if (!n_out) return fail(SMMO_EINVAL, "null n_out");
+    const smmo_raw_header& h = heap->hdr;
+    hipStream_t s = S(stream);
+    std::vector<uint8_t> raw(h.total_bytes);
+    HIP_TRY(hipMemcpyAsync(raw.data(), heap->base, h.total_bytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t* alloc = reinterpret_cast<const uint64_t*>(raw.data() + h.off_alloc);
+    const uint64_t* l0 = reinterpret_cast<const uint64_t*>(raw.data() + h.off_bitmaps) +
+                         (uint64_t)(1 + cls) * h.bitmap_words + h.level_off[0];
+    const uint64_t N = h.capacity[cls];
+    const uint64_t valid = N >= 64 ? ~0ull : ((1ull << N) - 1);
+    uint64_t n = 0;
+    for (uint64_t b = 0; b < h.num_blocks; ++b) {
+        if (!((l0[b >> 6] >> (b & 63)) & 1)) continue;
+        uint64_t w = alloc[b] & valid;
+        const uint8_t* blk = raw.data() + h.off_data + b * h.block_bytes;
+        while (w) {
+            uint32_t slot = (uint32_t)__builtin_ctzll(w);
+            w &= w - 1;
+            if (n < cap) {
+                if (refs) refs[n] = make_ref(cls, b, slot);
+                if (bufs)
+                    for (uint32_t f = 0; f < h.nfields[cls]; ++f) {
+                        if (!bufs[f]) continue;
+                        uint32_t fb = h.field_bytes[cls][f];
+                        std::memcpy(static_cast<uint8_t*>(bufs[f]) + n * fb, blk + h.field_off[cls][f] + slot * fb, fb);
+                    }
+            }
+            ++n;
+        }
+    }
+    *n_out = n;
+    return SMMO_OK;
+}
+
+int smmo_dump_objects(smmo_heap* heap, uint32_t cls, void* const* host_field_bufs, uint64_t cap, uint64_t* n_out,
+                      void* stream) {
+    return dump_walk(heap, cls, host_field_bufs, nullptr, cap, n_out, stream);
+}
+
+int smmo_dump_refs(smmo_heap* heap, uint32_t cls, uint64_t* host_refs, uint64_t cap, uint64_t* n_out,
+                   void* stream) {
+    return dump_walk(heap, cls, nullptr, host_refs, cap, n_out, stream);
+}
+
+int smmo_raw_bytes(const smmo_heap* heap, uint64_t* out) {
+    if (!heap || !out) return fail(SMMO_EINVAL, "null argument");
+    *out = heap->hdr.off_data;
+    return SMMO_OK;
+}
+
+int smmo_dump_raw(smmo_heap* heap, void* host_buf, uint64_t bytes, void* stream) {
+    if (!heap || !host_buf) return fail(SMMO_EINVAL, "null argument");
+    if (bytes < heap->hdr.off_data)
+        return fail(SMMO_EINVAL, "dump_raw: %llu bytes < %llu", (unsigned long long)bytes,
+                    (unsigned long long)heap->hdr.off_data);
+    hipStream_t s = S(stream);
+    HIP_TRY(hipMemcpyAsync(host_buf, heap->base, heap->hdr.off_data, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SMMO_OK;
+}
+
+int smmo_status(smmo_heap* heap, uint32_t* flags_out, void* stream) {
+    if (!heap || !flags_out) return fail(SMMO_EINVAL, "null argument");
+    hipStream_t s = S(stream);
+    HIP_TRY(hipMemcpyAsync(flags_out, heap->dev.status, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SMMO_OK;
+}
+
+int smmo_clear_status(smmo_heap* heap, void* stream) {
+    if (!heap) return fail(SMMO_EINVAL, "null argument");
+    hipStream_t s = S(stream);
+    // status word and counters: 256 bytes = 32 words, written by a kernel
+    k_fill_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long*>(heap->dev.status), 32, 0);
+    LAUNCH_CHECK("k_fill_u64");
+    return SMMO_OK;
+}
+
+int smmo_stats(smmo_heap* heap, uint64_t* out, uint32_t n, void* stream) {
+    if (!heap || !out || n > SMMO_CNT_NUM) return fail(SMMO_EINVAL, "bad argument");
+    hipStream_t s = S(stream);
+    HIP_TRY(hipMemcpyAsync(out, heap->dev.counters, 8ull * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SMMO_OK;
+}
+
+uint64_t smmo_ref_make(uint32_t cls, uint64_t block, uint32_t slot) { return make_ref(cls, block, slot); }
+uint32_t smmo_ref_class(uint64_t ref) { return ref_cls(ref); }
+uint64_t smmo_ref_block(uint64_t ref) { return ref_block(ref); }
+uint32_t smmo_ref_slot(uint64_t ref) { return ref_slot(ref); }
+
+const char* smmo_strerror(int code) {
+    switch (code) {
+        case SMMO_OK: return "ok";
+        case SMMO_EINVAL: return "invalid argument";
+        case SMMO_ETOOSMALL: return "device buffer too small";
+        case SMMO_ENOMEM_DEVICE: return "heap out of blocks";
+        case SMMO_ERETRY: return "retry bound exceeded";
+        case SMMO_EHIP: return "HIP runtime error";
+        case SMMO_ECORRUPT: return "heap corruption detected";
+        case SMMO_ENOTBUILT: return "variant not built";
+        default: return "unknown error";
+    }
+}
+
+const char* smmo_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,302 @@
+"""ctypes binding of libsmmo.so (include/smmo.h): argument marshalling only.
+
+Every operation runs in the library's HIP kernels; torch supplies the device
+buffer a heap lives in and the stream calls are queued on.  Importing this
+module fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsmmo.so")
+
+MAX_CLASSES = 16
+MAX_FIELDS = 16
+
+# constructors
+CTOR_ZERO = 0
+CTOR_ARRAYS = 1
+# methods
+M_AXPY = 0
+M_DESTROY_ALL = 1
+M_VISIT = 2
+M_CHURN = 3
+M_MIX = 4
+M_LIFE_PLAN = 10
+M_LIFE_AGENT = 11
+M_LIFE_COMMIT = 12
+M_WATOR_FISH_PLAN = 20
+M_WATOR_FISH_MOVE = 21
+M_WATOR_SHARK_PLAN = 22
+M_WATOR_SHARK_MOVE = 23
+# status bits
+STATUS_OOM = 1
+STATUS_RETRY = 2
+STATUS_CORRUPT = 4
+# tuning flags
+TUNE_NO_ROTATE = 1
+TUNE_NO_COALESCE = 2
+TUNE_STATS = 4
+TUNE_FORCE_FAIL = 8
+COUNTERS = ["alloc_obj", "free_obj", "block_init", "block_free", "inval_rollback", "type_rollback",
+            "find_fail", "reserve_fail", "spin", "reserve_atomic"]
+
+
+class ClassDesc(C.Structure):
+    _fields_ = [("nfields", C.c_uint32), ("field_bytes", C.POINTER(C.c_uint8))]
+
+
+class Layout(C.Structure):
+    _fields_ = [("capacity", C.c_uint32), ("nfields", C.c_uint32), ("block_bytes", C.c_uint64),
+                ("field_bytes", C.c_uint32 * MAX_FIELDS), ("field_offset", C.c_uint32 * MAX_FIELDS)]
+
+
+class CtorArrays(C.Structure):
+    _fields_ = [("src", C.c_void_p * MAX_FIELDS), ("ref_out", C.c_void_p), ("ref_index", C.c_void_p)]
+
+
+class AxpyArgs(C.Structure):
+    _fields_ = [("a", C.c_float), ("fx", C.c_uint32), ("fy", C.c_uint32), ("pad", C.c_uint32)]
+
+
+class VisitArgs(C.Structure):
+    _fields_ = [("visits", C.c_void_p)]
+
+
+class ChurnArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("round", C.c_uint32), ("pad", C.c_uint32)]
+
+
+class MixArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("round", C.c_uint32), ("cls_a", C.c_uint32), ("cls_b", C.c_uint32),
+                ("pad", C.c_uint32)]
+
+
+class LifeArgs(C.Structure):
+    _fields_ = [("cell_ref", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32),
+                ("cell_cls", C.c_uint32), ("agent_cls", C.c_uint32)]
+
+
+class WatorArgs(C.Structure):
+    _fields_ = [("occ", C.c_void_p), ("claim", C.c_void_p), ("want", C.c_void_p), ("seed", C.c_uint64),
+                ("width", C.c_int32), ("height", C.c_int32), ("step", C.c_int32),
+                ("fish_breed", C.c_int32), ("shark_breed", C.c_int32), ("eat_gain", C.c_int32),
+                ("shark_e0", C.c_int32), ("fish_cls", C.c_uint32), ("shark_cls", C.c_uint32),
+                ("pad", C.c_uint32)]
+
+
+class SmmoError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SmmoError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                            "or python paper_1810_11765_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, u32, u64, i = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+        sig = {
+            "smmo_heap_bytes": ([P, u32, u64, P], i),
+            "smmo_heap_create": ([P, u32, u64, P, u64, P, P], i),
+            "smmo_heap_destroy": ([P], i),
+            "smmo_heap_reset": ([P, P], i),
+            "smmo_class_layout": ([P, u32, P], i),
+            "smmo_layout_compute": ([P, u32, u32, P], i),
+            "smmo_set_tuning": ([P, u32, u32, u32, P], i),
+            "smmo_parallel_new": ([P, u32, u64, u32, P, u64, P], i),
+            "smmo_parallel_alloc": ([P, u32, u64, u32, u32, P, u64, P], i),
+            "smmo_parallel_do": ([P, u32, u32, P, u64, P], i),
+            "smmo_live_count": ([P, u32, P, P], i),
+            "smmo_dump_objects": ([P, u32, P, u64, P, P], i),
+            "smmo_dump_refs": ([P, u32, P, u64, P, P], i),
+            "smmo_raw_bytes": ([P, P], i),
+            "smmo_dump_raw": ([P, P, u64, P], i),
+            "smmo_status": ([P, P, P], i),
+            "smmo_clear_status": ([P, P], i),
+            "smmo_stats": ([P, P, u32, P], i),
+            "smmo_ref_make": ([u32, u64, u32], u64),
+            "smmo_ref_class": ([u64], u32),
+            "smmo_ref_block": ([u64], u64),
+            "smmo_ref_slot": ([u64], u32),
+            "smmo_strerror": ([i], C.c_char_p),
+            "smmo_last_error": ([], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        L = lib()
+        raise SmmoError(f"{L.smmo_strerror(rc).decode()} ({rc}): {L.smmo_last_error().decode()}")
+
+
+def _descs(classes):
+    arrs = [(C.c_uint8 * len(c))(*c) for c in classes]
+    descs = (ClassDesc * len(classes))()
+    for d, a, c in zip(descs, arrs, classes):
+        d.nfields = len(c)
+        d.field_bytes = C.cast(a, C.POINTER(C.c_uint8))
+    return descs, arrs
+
+
+def layout_of(classes, cls: int) -> Layout:
+    """Layout of class `cls` computed by the library without a heap."""
+    descs, _keep = _descs(classes)
+    out = Layout()
+    check(lib().smmo_layout_compute(descs, len(classes), cls, C.byref(out)))
+    return out
+
+
+def heap_bytes(classes, num_blocks: int) -> int:
+    descs, _keep = _descs(classes)
+    out = C.c_uint64()
+    check(lib().smmo_heap_bytes(descs, len(classes), num_blocks, C.byref(out)))
+    return out.value
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _blob(args):
+    if args is None:
+        return None, 0
+    return C.c_void_p(C.addressof(args)), C.sizeof(args)
+
+
+class Heap:
+    """A heap of `num_blocks` blocks for `classes` (lists of field byte sizes)
+    inside one torch uint8 device tensor owned by this object."""
+
+    def __init__(self, classes, num_blocks: int, device="cuda", stream=None):
+        import torch
+        self.classes = [list(c) for c in classes]
+        self.num_blocks = num_blocks
+        nbytes = heap_bytes(self.classes, num_blocks)
+        # 4 KiB slack so the buffer can be aligned to 256 bytes
+        self.buf = torch.empty(nbytes + 4096, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        self.offset = (-base) % 256
+        self.base = base + self.offset
+        self.nbytes = nbytes
+        descs, _keep = _descs(self.classes)
+        h = C.c_void_p()
+        check(lib().smmo_heap_create(descs, len(self.classes), num_blocks, C.c_void_p(self.base), nbytes,
+                                     _stream(stream), C.byref(h)))
+        self.h = h
+        self.layouts = [self.layout(t) for t in range(len(self.classes))]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().smmo_heap_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- queries
+    def layout(self, cls: int) -> Layout:
+        out = Layout()
+        check(lib().smmo_class_layout(self.h, cls, C.byref(out)))
+        return out
+
+    def capacity(self, cls: int) -> int:
+        return self.layouts[cls].capacity
+
+    def live_count(self, cls: int, stream=None) -> int:
+        out = C.c_uint64()
+        check(lib().smmo_live_count(self.h, cls, C.byref(out), _stream(stream)))
+        return out.value
+
+    def status(self, stream=None) -> int:
+        out = C.c_uint32()
+        check(lib().smmo_status(self.h, C.byref(out), _stream(stream)))
+        return out.value
+
+    def clear_status(self, stream=None) -> None:
+        check(lib().smmo_clear_status(self.h, _stream(stream)))
+
+    def stats(self, stream=None) -> dict:
+        out = (C.c_uint64 * 16)()
+        check(lib().smmo_stats(self.h, out, 16, _stream(stream)))
+        return {k: int(out[i]) for i, k in enumerate(COUNTERS)}
+
+    def set_tuning(self, flags: int = 0, lookups: int = 5, force_fail_ppm: int = 0, stream=None) -> None:
+        check(lib().smmo_set_tuning(self.h, flags, lookups, force_fail_ppm, _stream(stream)))
+
+    def reset(self, stream=None) -> None:
+        check(lib().smmo_heap_reset(self.h, _stream(stream)))
+
+    # -- operations
+    def parallel_new(self, cls: int, n: int, ctor: int = CTOR_ZERO, args=None, stream=None) -> None:
+        p, nb = _blob(args)
+        check(lib().smmo_parallel_new(self.h, cls, n, ctor, p, nb, _stream(stream)))
+
+    def parallel_alloc(self, cls: int, nthreads: int, per_thread: int, ctor: int = CTOR_ZERO, args=None,
+                       stream=None) -> None:
+        p, nb = _blob(args)
+        check(lib().smmo_parallel_alloc(self.h, cls, nthreads, per_thread, ctor, p, nb, _stream(stream)))
+
+    def parallel_do(self, cls: int, method: int, args=None, stream=None) -> None:
+        p, nb = _blob(args)
+        check(lib().smmo_parallel_do(self.h, cls, method, p, nb, _stream(stream)))
+
+    # -- dumps (synchronize)
+    def dump_objects(self, cls: int, dtypes, stream=None):
+        """Live objects of `cls` as a list of numpy arrays, one per field."""
+        n = self.live_count(cls, stream)
+        bufs = [np.zeros(max(n, 1), dtype=dt) for dt in dtypes]
+        assert [b.itemsize for b in bufs] == self.classes[cls], "dtype sizes must match the field sizes"
+        ptrs = (C.c_void_p * MAX_FIELDS)(*[b.ctypes.data for b in bufs])
+        got = C.c_uint64()
+        check(lib().smmo_dump_objects(self.h, cls, ptrs, n, C.byref(got), _stream(stream)))
+        assert got.value == n, (got.value, n)
+        return [b[:n] for b in bufs]
+
+    def dump_refs(self, cls: int, stream=None) -> np.ndarray:
+        n = self.live_count(cls, stream)
+        out = np.zeros(max(n, 1), dtype=np.uint64)
+        got = C.c_uint64()
+        check(lib().smmo_dump_refs(self.h, cls, out.ctypes.data, n, C.byref(got), _stream(stream)))
+        return out[: got.value]
+
+    def dump_raw(self, stream=None) -> bytes:
+        nb = C.c_uint64()
+        check(lib().smmo_raw_bytes(self.h, C.byref(nb)))
+        buf = np.zeros(nb.value, dtype=np.uint8)
+        check(lib().smmo_dump_raw(self.h, buf.ctypes.data, nb.value, _stream(stream)))
+        return buf.tobytes()
+
+
+def ctor_arrays(srcs, ref_out=None, ref_index=None) -> CtorArrays:
+    """Argument blob of CTOR_ARRAYS from device tensors (None = zero field)."""
+    a = CtorArrays()
+    for f, t in enumerate(srcs):
+        a.src[f] = None if t is None else t.data_ptr()
+    a.ref_out = None if ref_out is None else ref_out.data_ptr()
+    a.ref_index = None if ref_index is None else ref_index.data_ptr()
+    return a
+
+
+def ref_class(ref) -> np.ndarray:
+    return (np.asarray(ref, dtype=np.uint64) >> np.uint64(56)).astype(np.int64) - 1

@@ -1,0 +1,170 @@
+"""Host drivers of the SMMO workloads: set up heaps and issue the C-ABI calls.
+
+Each driver only uploads seeded starting states (paper_1810_11765_amd.inputs)
+and sequences parallel_new / parallel_alloc / parallel_do; every object
+operation runs in libsmmo's kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import inputs
+from . import smmo as S
+
+INT32_MAX = 2**31 - 1
+
+
+def _dev(a: np.ndarray, device="cuda") -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+class AllocBench:
+    """Alloc microbench: one class {int32 id, f32 x, f32 v}; `nthreads` threads
+    allocate `per_thread` objects each, then rounds of sweep + churn."""
+
+    CLASSES = [[4, 4, 4]]
+
+    def __init__(self, seed=42, num_blocks=4096, nthreads=65536, per_thread=4, device="cuda"):
+        self.seed, self.nthreads, self.per_thread = seed, nthreads, per_thread
+        self.heap = S.Heap(self.CLASSES, num_blocks, device=device)
+        ids, x, v = inputs.alloc_bench_initial(seed, nthreads, per_thread)
+        self.init_arrays = (ids, x, v)
+        self._src = [_dev(ids, device), _dev(x, device), _dev(v, device)]
+        self._sweep_args = S.AxpyArgs(0.5, 1, 2, 0)
+
+    def initial_alloc(self, stream=None):
+        self.heap.parallel_alloc(0, self.nthreads, self.per_thread, S.CTOR_ARRAYS,
+                                 S.ctor_arrays(self._src), stream=stream)
+
+    def initial_new(self, stream=None):
+        """Same objects through parallel_new (dense placement)."""
+        self.heap.parallel_new(0, self.nthreads * self.per_thread, S.CTOR_ARRAYS,
+                               S.ctor_arrays(self._src), stream=stream)
+
+    def sweep(self, stream=None):
+        self.heap.parallel_do(0, S.M_AXPY, self._sweep_args, stream=stream)
+
+    def churn(self, r: int, stream=None):
+        self.heap.parallel_do(0, S.M_CHURN, S.ChurnArgs(self.seed, r, 0), stream=stream)
+
+    def round(self, r: int, stream=None):
+        self.sweep(stream)
+        self.churn(r, stream)
+
+    def state(self):
+        ids, x, v = self.heap.dump_objects(0, [np.int32, np.float32, np.float32])
+        o = np.argsort(ids, kind="stable")
+        return ids[o], x[o], v[o]
+
+
+class LifeGrid:
+    """Life-like grid: Cell {int32 x, int32 y, int8 alive} (class 0) and
+    Agent {int32 cell, int32 age} (class 1) on a width x height torus."""
+
+    CLASSES = [[4, 4, 1], [4, 4]]
+    CELL, AGENT = 0, 1
+
+    def __init__(self, seed=42, width=512, height=512, num_blocks=16384, density=0.3, device="cuda",
+                 alive0: np.ndarray | None = None):
+        self.W, self.H = width, height
+        self.heap = S.Heap(self.CLASSES, num_blocks, device=device)
+        n = width * height
+        self.alive0 = inputs.life_initial(seed, width, height, density) if alive0 is None else alive0
+        c = np.arange(n, dtype=np.int32)
+        self._x = _dev((c % width).astype(np.int32), device)
+        self._y = _dev((c // width).astype(np.int32), device)
+        self._a = _dev(self.alive0.astype(np.uint8), device)
+        self.cell_ref = torch.zeros(n, dtype=torch.int64, device=device)
+        alive_ids = np.nonzero(self.alive0)[0].astype(np.int32)
+        self._agent_cell = _dev(alive_ids, device)
+        self.n_alive0 = len(alive_ids)
+        self.args = S.LifeArgs(self.cell_ref.data_ptr(), width, height, self.CELL, self.AGENT)
+
+    def populate(self, stream=None):
+        self.heap.parallel_new(self.CELL, self.W * self.H, S.CTOR_ARRAYS,
+                               S.ctor_arrays([self._x, self._y, self._a], ref_out=self.cell_ref), stream=stream)
+        if self.n_alive0:
+            self.heap.parallel_new(self.AGENT, self.n_alive0, S.CTOR_ARRAYS,
+                                   S.ctor_arrays([self._agent_cell, None]), stream=stream)
+
+    def step(self, stream=None):
+        self.heap.parallel_do(self.CELL, S.M_LIFE_PLAN, self.args, stream=stream)
+        self.heap.parallel_do(self.AGENT, S.M_LIFE_AGENT, self.args, stream=stream)
+        self.heap.parallel_do(self.CELL, S.M_LIFE_COMMIT, self.args, stream=stream)
+
+    def state(self):
+        """(alive grid uint8, agent age per cell with -1 where none)."""
+        x, y, a = self.heap.dump_objects(self.CELL, [np.int32, np.int32, np.uint8])
+        alive = np.zeros(self.W * self.H, dtype=np.uint8)
+        alive[y.astype(np.int64) * self.W + x] = a
+        cell, age = self.heap.dump_objects(self.AGENT, [np.int32, np.int32])
+        ages = np.full(self.W * self.H, -1, dtype=np.int32)
+        assert len(np.unique(cell)) == len(cell), "two agents on one cell"
+        ages[cell] = age
+        return alive, ages
+
+
+class WaTor:
+    """Predator-prey grid: Fish {int32 pos, int32 age} (class 0) and Shark
+    {int32 pos, int32 age, int32 energy} (class 1) on a width x height torus."""
+
+    CLASSES = [[4, 4], [4, 4, 4]]
+    FISH, SHARK = 0, 1
+
+    def __init__(self, seed=42, width=1024, height=1024, num_blocks=32768, fish=0.20, shark=0.05,
+                 fish_breed=3, shark_breed=8, eat_gain=4, shark_e0=4, device="cuda",
+                 kind0: np.ndarray | None = None):
+        self.seed, self.W, self.H = seed, width, height
+        self.params = dict(fish_breed=fish_breed, shark_breed=shark_breed, eat_gain=eat_gain, shark_e0=shark_e0)
+        self.heap = S.Heap(self.CLASSES, num_blocks, device=device)
+        n = width * height
+        self.kind0 = inputs.wator_initial(seed, width, height, fish, shark) if kind0 is None else kind0
+        self.occ = torch.zeros(n, dtype=torch.int64, device=device)
+        self.claim = torch.full((n,), INT32_MAX, dtype=torch.int32, device=device)
+        self.want = torch.zeros(n, dtype=torch.int32, device=device)
+        fpos = np.nonzero(self.kind0 == 1)[0].astype(np.int32)
+        spos = np.nonzero(self.kind0 == 2)[0].astype(np.int32)
+        self._f = [_dev(fpos, device), None]
+        self._s = [_dev(spos, device), None, _dev(np.full(len(spos), shark_e0, np.int32), device)]
+        self.nf0, self.ns0 = len(fpos), len(spos)
+        self.args = S.WatorArgs(self.occ.data_ptr(), self.claim.data_ptr(), self.want.data_ptr(),
+                                seed & (2**64 - 1), width, height, 0, fish_breed, shark_breed, eat_gain,
+                                shark_e0, self.FISH, self.SHARK, 0)
+        self.t = 0
+
+    def populate(self, stream=None):
+        if self.nf0:
+            self.heap.parallel_new(self.FISH, self.nf0, S.CTOR_ARRAYS,
+                                   S.ctor_arrays(self._f, ref_out=self.occ, ref_index=self._f[0]), stream=stream)
+        if self.ns0:
+            self.heap.parallel_new(self.SHARK, self.ns0, S.CTOR_ARRAYS,
+                                   S.ctor_arrays(self._s, ref_out=self.occ, ref_index=self._s[0]), stream=stream)
+
+    def step(self, stream=None):
+        self.t += 1
+        self.args.step = self.t
+        self.heap.parallel_do(self.FISH, S.M_WATOR_FISH_PLAN, self.args, stream=stream)
+        self.heap.parallel_do(self.FISH, S.M_WATOR_FISH_MOVE, self.args, stream=stream)
+        self.heap.parallel_do(self.SHARK, S.M_WATOR_SHARK_PLAN, self.args, stream=stream)
+        self.heap.parallel_do(self.SHARK, S.M_WATOR_SHARK_MOVE, self.args, stream=stream)
+
+    def state(self):
+        """(kind, age, energy) per cell, as the oracle reports them."""
+        n = self.W * self.H
+        kind = np.zeros(n, dtype=np.uint8)
+        age = np.zeros(n, dtype=np.int32)
+        energy = np.zeros(n, dtype=np.int32)
+        fp, fa = self.heap.dump_objects(self.FISH, [np.int32, np.int32])
+        sp, sa, se = self.heap.dump_objects(self.SHARK, [np.int32, np.int32, np.int32])
+        for p in (fp, sp):
+            assert len(np.unique(p)) == len(p), "two agents on one cell"
+        assert len(np.intersect1d(fp, sp)) == 0, "fish and shark on one cell"
+        kind[fp] = 1; age[fp] = fa
+        kind[sp] = 2; age[sp] = sa; energy[sp] = se
+        return kind, age, energy
+
+    def occ_kind(self) -> np.ndarray:
+        """Kind per cell as the occupancy grid records it (0 empty, 1+class)."""
+        occ = self.occ.cpu().numpy().view(np.uint64)
+        return np.where(occ == 0, 0, S.ref_class(occ) + 1).astype(np.uint8)

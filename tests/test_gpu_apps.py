@@ -1,0 +1,108 @@
+"""GPU parity of the SMMO application workloads (Life-like grid with agents,
+predator-prey grid) against the CPU oracle, through the C-ABI.  Integer
+workloads: bit-exact."""
+import numpy as np
+import pytest
+
+from helpers import check_heap, say
+from oracle import core
+from paper_1810_11765_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1810_11765_amd import smmo  # noqa: F401
+
+
+def W():
+    from paper_1810_11765_amd import workloads
+    return workloads
+
+
+def _life_check(g, W_, H_, steps_done):
+    alive, ages = g.state()
+    oa, oage = core.c2_run(g.alive0, W_, H_, steps_done)
+    assert np.array_equal(alive, oa), f"alive grid differs after {steps_done} steps"
+    assert np.array_equal(ages, oage), f"agent ages differ after {steps_done} steps"
+    check_heap(g.heap, expect_live=[W_ * H_, int(oa.sum())])
+
+
+@pytest.mark.parametrize("seed", [42, 7])
+def test_life_full_size_parity(seed):
+    """512 x 512 torus, density 0.3, 200 steps (16,384-block heap)."""
+    say("life 512", seed)
+    g = W().LifeGrid(seed=seed)
+    g.populate()
+    _life_check(g, 512, 512, 0)
+    for s in range(1, 201):
+        g.step()
+        if s in (1, 2, 50):
+            say("life step", s)
+            _life_check(g, 512, 512, s)
+    _life_check(g, 512, 512, 200)
+
+
+@pytest.mark.parametrize("Wd,Hd,blocks", [(37, 23, 64), (130, 7, 64), (64, 64, 128)])
+def test_life_ragged_parity(Wd, Hd, blocks):
+    say("life ragged", Wd, Hd)
+    g = W().LifeGrid(seed=3, width=Wd, height=Hd, num_blocks=blocks)
+    g.populate()
+    for s in range(60):
+        g.step()
+    _life_check(g, Wd, Hd, 60)
+
+
+def test_life_textbook_glider_on_gpu():
+    W_ = H_ = 16
+    a0 = np.zeros(W_ * H_, dtype=np.uint8)
+    for x, y in [(1, 0), (2, 1), (0, 2), (1, 2), (2, 2)]:
+        a0[y * W_ + x] = 1
+    g = W().LifeGrid(width=W_, height=H_, num_blocks=16, alive0=a0)
+    g.populate()
+    for _ in range(4):
+        g.step()
+    alive, ages = g.state()
+    want = np.zeros_like(a0)
+    for x, y in [(2, 1), (3, 2), (1, 3), (2, 3), (3, 3)]:
+        want[y * W_ + x] = 1
+    assert np.array_equal(alive, want)
+
+
+def _wator_check(w, steps_done, oracle_state):
+    kind, age, energy = w.state()
+    ok, oa, oe = oracle_state
+    assert np.array_equal(kind, ok), f"occupancy differs after {steps_done} steps"
+    assert np.array_equal(age[kind > 0], oa[ok > 0]), f"ages differ after {steps_done} steps"
+    assert np.array_equal(energy[kind == 2], oe[ok == 2]), f"energies differ after {steps_done} steps"
+    assert np.array_equal(w.occ_kind(), kind), "occupancy grid disagrees with the live objects"
+    check_heap(w.heap, expect_live=[int((ok == 1).sum()), int((ok == 2).sum())])
+
+
+@pytest.mark.parametrize("seed", [42, 7, 1234])
+def test_wator_full_size_parity(seed):
+    """1024 x 1024 torus, 20% fish, 5% sharks, 500 steps (32,768-block heap)."""
+    say("wator 1024", seed)
+    w = W().WaTor(seed=seed)
+    w.populate()
+    assert np.array_equal(w.kind0, inputs.wator_initial(seed, 1024, 1024))
+    for s in range(1, 501):
+        w.step()
+        if s in (1, 25, 500):
+            say("wator step", s)
+            _wator_check(w, s, core.c3_run(w.kind0, 1024, 1024, seed, s))
+
+
+@pytest.mark.parametrize("Wd,Hd,blocks,seed", [(97, 61, 256, 5), (16, 200, 128, 6), (8, 8, 8, 7)])
+def test_wator_ragged_parity(Wd, Hd, blocks, seed):
+    say("wator ragged", Wd, Hd)
+    w = W().WaTor(seed=seed, width=Wd, height=Hd, num_blocks=blocks)
+    w.populate()
+    for s in range(120):
+        w.step()
+    _wator_check(w, 120, core.c3_run(w.kind0, Wd, Hd, seed, 120))

@@ -1,0 +1,96 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol,
+and its host-side logic (layout, sizes, argument checks, handles) matches the
+paper's formulas as restated by the oracle.  No kernel is launched."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from oracle import heapcheck, layout_ref
+from paper_1810_11765_amd import smmo as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "smmo.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(smmo_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 20
+    L = C.CDLL(S.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", S.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (smmo_\w+)", out))
+    assert set(names) <= exported
+
+
+WORKLOAD_CLASSES = [
+    [[4, 4, 4]],                 # alloc microbench
+    [[4, 4, 1], [4, 4]],         # Life: Cell, Agent
+    [[4, 4], [4, 4, 4]],         # Wa-Tor: Fish, Shark
+    [[4] * 5],                   # n-body
+    [[1, 2], [8, 8, 8, 8], [4]],
+    [[1], [8] * 8],              # exactly 64x
+]
+
+
+@pytest.mark.parametrize("classes", WORKLOAD_CLASSES)
+def test_layout_matches_capacity_formula(classes):
+    block, per = layout_ref.layout(classes)
+    for t, (n, offs) in enumerate(per):
+        lay = S.layout_of(classes, t)
+        assert lay.capacity == n
+        assert lay.block_bytes == block
+        assert list(lay.field_offset[: len(offs)]) == offs
+        assert list(lay.field_bytes[: len(offs)]) == classes[t]
+
+
+def test_layout_rejects_bad_classes():
+    for bad in ([[1], [8] * 9], [[3]], [[]], [[4]] * 17):
+        with pytest.raises(S.SmmoError):
+            S.layout_of(bad, 0)
+
+
+def test_heap_bytes_and_header_struct_offsets(tmp_path):
+    # bytes grow with blocks by exactly block_bytes (data) + per-block words
+    b1 = S.heap_bytes([[4, 4, 4]], 4096)
+    b2 = S.heap_bytes([[4, 4, 4]], 8192)
+    assert b2 - b1 >= 4096 * (768 + 20)
+    # the checker's parser offsets agree with the C struct layout
+    prog = str(tmp_path / "hdr_offsets")
+    src = prog + ".c"
+    with open(src, "w") as f:
+        f.write('#include <stdio.h>\n#include <stddef.h>\n#include "smmo.h"\n'
+                '#define P(x) printf("%zu ", offsetof(smmo_raw_header, x));\n'
+                "int main(){P(magic)P(num_blocks)P(ncls)P(block_bytes)P(nlevels)P(level_words)P(level_off)"
+                "P(bitmap_words)P(off_status)P(off_type)P(off_alloc)P(off_iter)P(off_bitmaps)P(off_scratch)"
+                "P(scratch_bytes)P(off_data)P(total_bytes)P(capacity)P(nfields)P(field_bytes)P(field_off)"
+                "P(tune_flags)P(lookups)P(force_fail_ppm)return 0;}\n")
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", prog], check=True)
+    got = [int(v) for v in subprocess.run([prog], capture_output=True, text=True).stdout.split()]
+    assert got == [0, 16, 24, 32, 40, 48, 96, 144, 152, 160, 168, 176, 184, 192, 200, 208, 216, 224, 352, 480,
+                   1504, 2528, 2532, 2536]
+    assert heapcheck.MAGIC == 0x504145484F4D4D53
+
+
+def test_handle_encoding():
+    L = S.lib()
+    for cls, blk, slot in ((0, 0, 0), (3, 12345, 63), (15, (1 << 44) - 1, 7)):
+        r = L.smmo_ref_make(cls, blk, slot)
+        assert r != 0
+        assert (L.smmo_ref_class(r), L.smmo_ref_block(r), L.smmo_ref_slot(r)) == (cls, blk, slot)
+        assert int(S.ref_class(r)) == cls
+
+
+def test_strerror_codes():
+    L = S.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert L.smmo_strerror(code)
