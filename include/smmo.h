@@ -193,6 +193,7 @@ typedef struct smmo_ctor_arrays {
 #define SMMO_M_VISIT 2u             /* visits[id field 0] += 1        (smmo_visit_args) */
 #define SMMO_M_CHURN 3u             /* alloc microbench round         (smmo_churn_args) */
 #define SMMO_M_MIX 4u               /* two-class churn (test method)  (smmo_mix_args)   */
+#define SMMO_M_STRESS 5u            /* alloc/destroy storm (test)     (smmo_stress_args) */
 #define SMMO_M_LIFE_PLAN 10u        /* Cell: next state, B3/S23       (smmo_life_args)  */
 #define SMMO_M_LIFE_AGENT 11u       /* Agent: die or age              (smmo_life_args)  */
 #define SMMO_M_LIFE_COMMIT 12u      /* Cell: birth of agents, commit  (smmo_life_args)  */
@@ -200,6 +201,12 @@ typedef struct smmo_ctor_arrays {
 #define SMMO_M_WATOR_FISH_MOVE 21u  /* Fish: move, breed              (smmo_wator_args) */
 #define SMMO_M_WATOR_SHARK_PLAN 22u /* Shark: age, choose and claim   (smmo_wator_args) */
 #define SMMO_M_WATOR_SHARK_MOVE 23u /* Shark: move, eat, breed, starve(smmo_wator_args) */
+#define SMMO_M_NBODY_INSERT 30u     /* Body: enter the cell hash grid (smmo_nbody_args) */
+#define SMMO_M_NBODY_PAIRS 31u      /* Body: list close pairs         (smmo_nbody_args) */
+#define SMMO_M_NBODY_RESOLVE 32u    /* class phase: merge components  (smmo_nbody_args) */
+#define SMMO_M_NBODY_REAP 33u       /* Body: merged bodies destroy themselves, grid reset */
+#define SMMO_M_NBODY_FORCE 34u      /* Body: all-pairs force via device_do, v += a*dt   */
+#define SMMO_M_NBODY_MOVE 35u       /* Body: x += v*dt                                  */
 
 /* y += a*x on float32 fields fx, fy of the class (one rounding: a*x is formed
  * first, then added). */
@@ -226,6 +233,19 @@ typedef struct smmo_mix_args {
     uint32_t pad;
 } smmo_mix_args;
 
+/* Allocation storm (test method that forces the races of App. A.3-A.4):
+ * every wave of the do-all runs `iters` rounds; in round k the lanes whose
+ * slot is below `lanes` allocate one object each, in cls_b if bit 0 of
+ * splitmix64(seed ^ (key << 20) ^ k) is set else in cls_a, write the
+ * allocating object's key into field 0, and destroy it again in the same
+ * round.  The driver objects are not changed.  Classes a and b need an int32
+ * field 0; at the end no object of either class remains. */
+typedef struct smmo_stress_args {
+    uint64_t seed;
+    uint32_t iters, lanes;
+    uint32_t cls_a, cls_b;
+} smmo_stress_args;
+
 /* Life-like grid on a width x height torus.  Cell {int32 x, int32 y, int8
  * alive}: alive bit 0 = current, bit 1 = next.  Agent {int32 cell, int32 age}.
  * cell_ref[c] is the handle of cell c = y*width + x (device array). */
@@ -250,6 +270,38 @@ typedef struct smmo_wator_args {
     uint32_t fish_cls, shark_cls;
     uint32_t pad;
 } smmo_wator_args;
+
+/* N-body with merging (the collision app of Sec. 1 and Table 1) on a class
+ * Body {f32 x, f32 y, f32 vx, f32 vy, f32 m} created by one parallel_new, so
+ * that ascending (block, slot) order is ascending creation index; the body's
+ * key is block*64 + slot.  One step = INSERT, PAIRS, RESOLVE, REAP, FORCE,
+ * MOVE, all with the same argument blob:
+ *  INSERT   put each body into a hashed uniform grid (cell 1/inv_cell)
+ *  PAIRS    list every pair closer than merge_dist (sqrtf of the squared
+ *           distance, compared with <), lower key first
+ *  RESOLVE  join the pairs into connected components; the lowest key keeps
+ *           its position and gets m = sum m_k, v = (sum m_k v_k) / m, both
+ *           summed in ascending key; every other member is marked merged
+ *  REAP     merged bodies destroy themselves (Listing 1, step_6_delete_merged)
+ *  FORCE    a_i = sum over live j != i in ascending key of
+ *           s*(x_j - x_i, y_j - y_i), s = (G*m_j) / (d2*sqrtf(d2)),
+ *           d2 = dx*dx + dy*dy (device_do over all bodies, Sec. 2.1); v += a*dt
+ *  MOVE     x += v*dt
+ * Scratch arrays are caller device memory: head[1 << hash_bits] (all -1 and
+ * npairs 0 before the first step; every step leaves them so), next, lab and
+ * merged with num_blocks*64 entries (merged all 0), pairs[2*pair_cap].  More
+ * than pair_cap close pairs in one step sets SMMO_STATUS_CORRUPT. */
+typedef struct smmo_nbody_args {
+    int32_t* head;
+    int32_t* next;
+    int32_t* lab;
+    uint8_t* merged;
+    int32_t* pairs;
+    uint32_t* npairs;
+    uint32_t hash_bits;
+    uint32_t pair_cap;
+    float G, dt, merge_dist, inv_cell;
+} smmo_nbody_args;
 
 /* -------------------------------------------------------- operations ---- */
 

@@ -113,3 +113,16 @@ def c4_accel(x, y, m, sel, G=1e-6):
     ay = np.zeros(len(sel), dtype=np.float32)
     lib().or_c4_accel(len(x), _p(x), _p(y), _p(m), G, len(sel), _p(sel), _p(ax), _p(ay))
     return ax, ay
+
+
+def c4_merge_grid(ids, x, y, vx, vy, m, merge_dist=1e-4, cell=1.0 / 1024):
+    """Merge phase only (grid candidates, same float test); returns survivors and #pairs."""
+    L = lib()
+    if not hasattr(L, "_merge_sig"):
+        L.or_c4_merge_grid.argtypes = [C.c_int64] + [C.c_void_p] * 6 + [C.c_float, C.c_double, C.c_void_p]
+        L.or_c4_merge_grid.restype = C.c_int64
+        L._merge_sig = True
+    arrs = [np.ascontiguousarray(a).copy() for a in (ids, x, y, vx, vy, m)]
+    npairs = np.zeros(1, dtype=np.int64)
+    n = L.or_c4_merge_grid(len(arrs[0]), *[_p(a) for a in arrs], merge_dist, cell, _p(npairs))
+    return tuple(a[:n].copy() for a in arrs), int(npairs[0])

@@ -360,3 +360,75 @@ void or_c4_accel(int64_t n, const float* x, const float* y, const float* m, floa
         ax[q] = sx; ay[q] = sy;
     }
 }
+
+/* Merge phase (M) alone, for checking a large state: the same rule as in
+ * or_c4_step, with candidate pairs taken from a uniform grid of cell edge
+ * `cell` >= merge_dist (two bodies closer than merge_dist are in the same or
+ * in adjacent cells), each candidate decided by the same float test.
+ * Returns the survivor count; arrays are compacted in place. */
+typedef struct { int64_t cx, cy, i; } or_cellrec;
+static int cmp_cellrec(const void* a, const void* b)
+{
+    const or_cellrec* p = (const or_cellrec*)a; const or_cellrec* q = (const or_cellrec*)b;
+    if (p->cx != q->cx) return p->cx < q->cx ? -1 : 1;
+    if (p->cy != q->cy) return p->cy < q->cy ? -1 : 1;
+    return (p->i > q->i) - (p->i < q->i);
+}
+
+int64_t or_c4_merge_grid(int64_t n, int32_t* id, float* x, float* y, float* vx, float* vy, float* m,
+                         float merge_dist, double cell, int64_t* npairs_out)
+{
+    or_cellrec* rec = (or_cellrec*)malloc(sizeof(or_cellrec) * (size_t)(n ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        rec[i].cx = (int64_t)floor((double)x[i] / cell);
+        rec[i].cy = (int64_t)floor((double)y[i] / cell);
+        rec[i].i = i;
+    }
+    qsort(rec, (size_t)n, sizeof(or_cellrec), cmp_cellrec);
+    int64_t* par = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    for (int64_t i = 0; i < n; ++i) par[i] = i;
+    int64_t npairs = 0;
+    for (int64_t a = 0; a < n; ++a) {
+        for (int64_t dx = -1; dx <= 1; ++dx)
+            for (int64_t dy = -1; dy <= 1; ++dy) {
+                or_cellrec key = { rec[a].cx + dx, rec[a].cy + dy, -1 };
+                /* first record of that cell */
+                int64_t lo = 0, hi = n;
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) / 2;
+                    if (cmp_cellrec(&rec[mid], &key) < 0) lo = mid + 1; else hi = mid;
+                }
+                for (int64_t b = lo; b < n && rec[b].cx == key.cx && rec[b].cy == key.cy; ++b) {
+                    int64_t i = rec[a].i, j = rec[b].i;
+                    if (j <= i) continue;              /* each pair once, i < j */
+                    float ddx = x[j] - x[i], ddy = y[j] - y[i];
+                    float d = sqrtf(ddx * ddx + ddy * ddy);
+                    if (d < merge_dist) {
+                        int64_t ra = uf_find(par, i), rb = uf_find(par, j);
+                        if (ra < rb) par[rb] = ra; else if (rb < ra) par[ra] = rb;
+                        ++npairs;
+                    }
+                }
+            }
+    }
+    if (npairs_out) *npairs_out = npairs;
+    float* ms = (float*)malloc(sizeof(float) * (size_t)(n ? n : 1));
+    float* px = (float*)malloc(sizeof(float) * (size_t)(n ? n : 1));
+    float* py = (float*)malloc(sizeof(float) * (size_t)(n ? n : 1));
+    int32_t* cnt = (int32_t*)calloc((size_t)(n ? n : 1), sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t r = uf_find(par, i);
+        if (cnt[r]++ == 0) { ms[r] = m[i]; px[r] = m[i] * vx[i]; py[r] = m[i] * vy[i]; }
+        else { ms[r] = ms[r] + m[i]; px[r] = px[r] + m[i] * vx[i]; py[r] = py[r] + m[i] * vy[i]; }
+    }
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (uf_find(par, i) != i) continue;
+        id[k] = id[i]; x[k] = x[i]; y[k] = y[i];
+        if (cnt[i] > 1) { m[k] = ms[i]; vx[k] = px[i] / ms[i]; vy[k] = py[i] / ms[i]; }
+        else { m[k] = m[i]; vx[k] = vx[i]; vy[k] = vy[i]; }
+        ++k;
+    }
+    free(rec); free(par); free(ms); free(px); free(py); free(cnt);
+    return k;
+}

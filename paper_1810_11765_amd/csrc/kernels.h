@@ -119,9 +119,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls
 }
 
 // ------------------------------------------------------ parallel_new ----
-// Lowest `nb` free blocks in ascending order -> R[0..nb); *found = how many.
+// The first `nb` set bits of block bitmap `bmid` in ascending order -> R[0..nb)
+// (Sec. 3.7, the ordered compaction of Fig. "scan_enumeration"); *found =
+// how many were written.  parallel_new uses it on the free bitmap, the n-body
+// force phase on allocated[T].
 // One workgroup; each thread scans a contiguous range of L0 words.
-__global__ __launch_bounds__(1024) void k_find_free(DevHeap h, uint64_t nb, uint32_t* R,
+__global__ __launch_bounds__(1024) void k_enum(DevHeap h, uint32_t bmid, uint64_t nb, uint32_t* R,
                                                     unsigned long long* found) {
     __shared__ unsigned long long wsum[16];
     __shared__ unsigned long long total_s;
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(1024) void k_find_free(DevHeap h, uint64_t nb, uint
     const uint64_t W0 = (h.M + 63) >> 6;
     const uint64_t per = (W0 + 1023) / 1024;
     const uint64_t lo = (uint64_t)t * per, hi = lo + per < W0 ? lo + per : W0;
-    const uint64_t* l0 = bm_word(h, bm_free(), 0, 0);
+    const uint64_t* l0 = bm_word(h, bmid, 0, 0);
     unsigned long long cnt = 0;
     for (uint64_t i = lo; i < hi; ++i) cnt += popc64(l0[i]);
     // inclusive scan inside the wave

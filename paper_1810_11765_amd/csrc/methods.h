@@ -30,6 +30,67 @@ struct MAxpy {
     }
 };
 
+// Streaming form of the same do-all for the HBM-bound sweep.  The method only
+// reads and writes its own object's fields and creates / destroys nothing, so
+// four blocks can share a wave: lanes 16g..16g+15 take block g of the group,
+// each lane four consecutive slots with 16-byte loads and stores (one 256-B
+// SOA segment per 16 lanes).  A wave owns a unit of one L0 word of
+// allocated[T]; it fetches the unit's 64 allocation words with one coalesced
+// load and walks the word's set bits eight blocks at a time, so eight blocks'
+// loads are in flight before the first store.  A dead slot keeps its bytes
+// (the old value is stored back), which is safe because nothing else writes
+// this class's slots during the do-all.
+template <int kGroups>
+__global__ __launch_bounds__(kBlockThreads) void k_doall_axpy(DevHeap h, uint32_t cls, uint64_t nwords,
+                                                               smmo_axpy_args a) {
+    const uint32_t lane = lane_id();
+    const uint32_t g = lane >> 4, q = lane & 15;          // block of the group, lane within it
+    const uint64_t wave = global_wave();
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t* l0 = bm_word(h, bm_allocated(cls), 0, 0);
+    const uint64_t valid = ~h.cls_pad[cls];
+    const uint32_t N = h.cls_cap[cls];
+    const uint32_t ox = h.hdr->field_off[cls][a.fx], oy = h.hdr->field_off[cls][a.fy];
+    const bool in_cap = 4 * q < N;
+    for (uint64_t w = wave; w < nwords; w += nwaves) {
+        const uint64_t word = l0[w];
+        if (!word) continue;
+        // allocation word of block w*64 + lane
+        const uint64_t my_alloc = ((word >> lane) & 1) ? h.alloc[(w << 6) | lane] : 0;
+        const uint32_t nb = popc64(word);
+        for (uint32_t base = 0; base < nb; base += 4 * kGroups) {
+            float4 xv[kGroups], yv[kGroups];
+            uint32_t live4[kGroups];
+            float4* py[kGroups];
+#pragma unroll
+            for (int u = 0; u < kGroups; ++u) {
+                const uint32_t k = base + 4 * u + g;           // k-th block of the word
+                const bool have = k < nb && in_cap;
+                const uint32_t b = have ? nth_set_bit(word, k) : 0;
+                const uint64_t live = (uint64_t)__shfl((unsigned long long)my_alloc, (int)b, 64) & valid;
+                live4[u] = have ? (uint32_t)((live >> (4 * q)) & 0xF) : 0;
+                uint8_t* blk = h.data + ((w << 6) | b) * h.block_bytes;
+                py[u] = reinterpret_cast<float4*>(blk + oy) + q;
+                if (live4[u]) {
+                    xv[u] = reinterpret_cast<const float4*>(blk + ox)[q];
+                    yv[u] = *py[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kGroups; ++u) {
+                if (!live4[u]) continue;
+                float4 r = yv[u];
+                const uint32_t m = live4[u];
+                if (m & 1) r.x = yv[u].x + a.a * xv[u].x;
+                if (m & 2) r.y = yv[u].y + a.a * xv[u].y;
+                if (m & 4) r.z = yv[u].z + a.a * xv[u].z;
+                if (m & 8) r.w = yv[u].w + a.a * xv[u].w;
+                *py[u] = r;
+            }
+        }
+    }
+}
+
 // Every object destroys itself (the deallocation kernel of the allocation
 // microbenchmarks, Sec. 6.4).
 struct MDestroyAll {
@@ -122,6 +183,28 @@ struct MMix {
         if (die && r) {
             field_of<int32_t>(o.h, r, 0) = nid;
             zero_rest(o.h, r);
+        }
+    }
+};
+
+// Allocation storm on a tiny heap: many waves allocate into and free the same
+// few blocks at once, so blocks empty, get invalidated, freed and
+// re-initialized to the other class while other waves hold stale picks.
+struct MStress {
+    using Args = smmo_stress_args;
+    static constexpr bool kSnapshot = false;
+    struct Prep { uint32_t unused; };
+    __device__ static Prep prepare(const DevHeap&, uint32_t, const Args&) { return {0}; }
+    __device__ static void run(const Obj& o, const Prep&, const Args& a) {
+        const uint32_t key = (uint32_t)(o.bid * 64 + o.lane);
+        for (uint32_t k = 0; k < a.iters; ++k) {
+            const bool act = o.live && o.lane < a.lanes;
+            const bool to_b = splitmix64(a.seed ^ ((uint64_t)key << 20) ^ k) & 1;
+            const uint64_t ra = wave_alloc(o.h, a.cls_a, act && !to_b, o.seed ^ k);
+            const uint64_t rb = wave_alloc(o.h, a.cls_b, act && to_b, o.seed ^ (k << 8) ^ 0x51ull);
+            const uint64_t r = to_b ? rb : ra;
+            if (act && r) field_of<int32_t>(o.h, r, 0) = (int32_t)key;
+            wave_destroy(o.h, r, act && r != 0);
         }
     }
 };

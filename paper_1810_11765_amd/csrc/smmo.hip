@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "methods.h"
+#include "nbody.h"
 
 using namespace smmo;
 
@@ -224,6 +225,46 @@ int launch_doall(smmo_heap* H, uint32_t cls, const void* args, uint64_t bytes, h
     return SMMO_OK;
 }
 
+int check_nbody(const smmo_heap* H, uint32_t cls, const smmo_nbody_args& a) {
+    if (H->hdr.nfields[cls] != 5) return fail(SMMO_EINVAL, "n-body: class needs 5 float32 fields");
+    for (int f = 0; f < 5; ++f)
+        if (H->hdr.field_bytes[cls][f] != 4) return fail(SMMO_EINVAL, "n-body: class needs 5 float32 fields");
+    if (H->hdr.num_blocks * 64 > (uint64_t)INT32_MAX) return fail(SMMO_EINVAL, "n-body: keys exceed int32");
+    if (!a.head || !a.next || !a.lab || !a.merged || !a.pairs || !a.npairs)
+        return fail(SMMO_EINVAL, "n-body: null scratch array");
+    if (a.hash_bits < 1 || a.hash_bits > 30) return fail(SMMO_EINVAL, "n-body: hash_bits must be 1..30");
+    if (!(a.inv_cell > 0.0f) || !(a.merge_dist * a.inv_cell <= 1.0f))
+        return fail(SMMO_EINVAL, "n-body: grid cell must be at least merge_dist");
+    return SMMO_OK;
+}
+
+int launch_nbody(smmo_heap* H, uint32_t cls, uint32_t method, const void* args, uint64_t bytes, hipStream_t s) {
+    smmo_nbody_args a;
+    int rc = unpack_args(a, args, bytes, "n-body");
+    if (rc) return rc;
+    rc = check_nbody(H, cls, a);
+    if (rc) return rc;
+    switch (method) {
+        case SMMO_M_NBODY_INSERT: return launch_doall<MNbInsert>(H, cls, args, bytes, s);
+        case SMMO_M_NBODY_PAIRS: return launch_doall<MNbPairs>(H, cls, args, bytes, s);
+        case SMMO_M_NBODY_REAP: return launch_doall<MNbReap>(H, cls, args, bytes, s);
+        case SMMO_M_NBODY_MOVE: return launch_doall<MNbMove>(H, cls, args, bytes, s);
+        case SMMO_M_NBODY_RESOLVE:
+            k_nbody_resolve<<<1, 1024, 0, s>>>(H->dev, cls, a);
+            LAUNCH_CHECK("k_nbody_resolve");
+            return SMMO_OK;
+        case SMMO_M_NBODY_FORCE:
+            k_enum<<<1, 1024, 0, s>>>(H->dev, bm_allocated(cls), H->hdr.num_blocks, scratch_R(H),
+                                       scratch_counter(H, 2));
+            LAUNCH_CHECK("k_enum");
+            k_nbody_force<<<grid_for(H->hdr.num_blocks, 4), 256, 0, s>>>(H->dev, cls, scratch_R(H),
+                                                                         scratch_counter(H, 2), a);
+            LAUNCH_CHECK("k_nbody_force");
+            return SMMO_OK;
+        default: return fail(SMMO_EINVAL, "unknown n-body method %u", method);
+    }
+}
+
 template <class C>
 int launch_new(smmo_heap* H, uint32_t cls, uint64_t n, const void* args, uint64_t bytes, hipStream_t s) {
     typename C::Args a;
@@ -234,8 +275,8 @@ int launch_new(smmo_heap* H, uint32_t cls, uint64_t n, const void* args, uint64_
     if (nb > H->hdr.num_blocks) return fail(SMMO_EINVAL, "parallel_new: %llu objects need %llu blocks, heap has %llu",
                                             (unsigned long long)n, (unsigned long long)nb,
                                             (unsigned long long)H->hdr.num_blocks);
-    k_find_free<<<1, 1024, 0, s>>>(H->dev, nb, scratch_R(H), scratch_counter(H, 0));
-    LAUNCH_CHECK("k_find_free");
+    k_enum<<<1, 1024, 0, s>>>(H->dev, bm_free(), nb, scratch_R(H), scratch_counter(H, 0));
+    LAUNCH_CHECK("k_enum");
     k_new_fill<C><<<grid_for(nb * 64, kBlockThreads), kBlockThreads, 0, s>>>(H->dev, cls, n, scratch_R(H),
                                                                               scratch_counter(H, 0), a);
     LAUNCH_CHECK("k_new_fill");
@@ -376,7 +417,11 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
             if (a.fx >= heap->hdr.nfields[cls] || a.fy >= heap->hdr.nfields[cls] ||
                 heap->hdr.field_bytes[cls][a.fx] != 4 || heap->hdr.field_bytes[cls][a.fy] != 4)
                 return fail(SMMO_EINVAL, "axpy: fields must be 4-byte fields of the class");
-            return launch_doall<MAxpy>(heap, cls, args, args_bytes, s);
+            const uint64_t nwords = heap->hdr.level_words[0];
+            const uint64_t waves = std::min<uint64_t>(nwords, 256ull * 32);
+            k_doall_axpy<2><<<(unsigned)((waves + 3) / 4), kBlockThreads, 0, s>>>(heap->dev, cls, nwords, a);
+            LAUNCH_CHECK("k_doall_axpy");
+            return SMMO_OK;
         }
         case SMMO_M_DESTROY_ALL: return launch_doall<MDestroyAll>(heap, cls, nullptr, 0, s);
         case SMMO_M_VISIT: return launch_doall<MVisit>(heap, cls, args, args_bytes, s);
@@ -390,6 +435,15 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
                 return fail(SMMO_EINVAL, "mix: classes need an int32 field 0");
             return launch_doall<MMix>(heap, cls, args, args_bytes, s);
         }
+        case SMMO_M_STRESS: {
+            smmo_stress_args a;
+            rc = unpack_args(a, args, args_bytes, "stress");
+            if (rc) return rc;
+            if (a.cls_a >= heap->hdr.ncls || a.cls_b >= heap->hdr.ncls || a.cls_a == cls || a.cls_b == cls ||
+                heap->hdr.field_bytes[a.cls_a][0] != 4 || heap->hdr.field_bytes[a.cls_b][0] != 4 || a.lanes > 64)
+                return fail(SMMO_EINVAL, "stress: two other classes with an int32 field 0, lanes <= 64");
+            return launch_doall<MStress>(heap, cls, args, args_bytes, s);
+        }
         case SMMO_M_LIFE_PLAN: return launch_doall<MLifePlan>(heap, cls, args, args_bytes, s);
         case SMMO_M_LIFE_AGENT: return launch_doall<MLifeAgent>(heap, cls, args, args_bytes, s);
         case SMMO_M_LIFE_COMMIT: return launch_doall<MLifeCommit>(heap, cls, args, args_bytes, s);
@@ -397,6 +451,12 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
         case SMMO_M_WATOR_FISH_MOVE: return launch_doall<MFishMove>(heap, cls, args, args_bytes, s);
         case SMMO_M_WATOR_SHARK_PLAN: return launch_doall<MSharkPlan>(heap, cls, args, args_bytes, s);
         case SMMO_M_WATOR_SHARK_MOVE: return launch_doall<MSharkMove>(heap, cls, args, args_bytes, s);
+        case SMMO_M_NBODY_INSERT:
+        case SMMO_M_NBODY_PAIRS:
+        case SMMO_M_NBODY_RESOLVE:
+        case SMMO_M_NBODY_REAP:
+        case SMMO_M_NBODY_FORCE:
+        case SMMO_M_NBODY_MOVE: return launch_nbody(heap, cls, method_id, args, args_bytes, s);
         default: return fail(SMMO_EINVAL, "unknown method_id %u", method_id);
     }
 }

@@ -300,3 +300,27 @@ def ctor_arrays(srcs, ref_out=None, ref_index=None) -> CtorArrays:
 
 def ref_class(ref) -> np.ndarray:
     return (np.asarray(ref, dtype=np.uint64) >> np.uint64(56)).astype(np.int64) - 1
+
+
+M_NBODY_INSERT = 30
+M_NBODY_PAIRS = 31
+M_NBODY_RESOLVE = 32
+M_NBODY_REAP = 33
+M_NBODY_FORCE = 34
+M_NBODY_MOVE = 35
+NBODY_PHASES = (M_NBODY_INSERT, M_NBODY_PAIRS, M_NBODY_RESOLVE, M_NBODY_REAP, M_NBODY_FORCE, M_NBODY_MOVE)
+
+
+class NbodyArgs(C.Structure):
+    _fields_ = [("head", C.c_void_p), ("next", C.c_void_p), ("lab", C.c_void_p), ("merged", C.c_void_p),
+                ("pairs", C.c_void_p), ("npairs", C.c_void_p), ("hash_bits", C.c_uint32),
+                ("pair_cap", C.c_uint32), ("G", C.c_float), ("dt", C.c_float), ("merge_dist", C.c_float),
+                ("inv_cell", C.c_float)]
+
+
+M_STRESS = 5
+
+
+class StressArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("iters", C.c_uint32), ("lanes", C.c_uint32), ("cls_a", C.c_uint32),
+                ("cls_b", C.c_uint32)]

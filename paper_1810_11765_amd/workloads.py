@@ -168,3 +168,54 @@ class WaTor:
         """Kind per cell as the occupancy grid records it (0 empty, 1+class)."""
         occ = self.occ.cpu().numpy().view(np.uint64)
         return np.where(occ == 0, 0, S.ref_class(occ) + 1).astype(np.uint8)
+
+
+class NBody:
+    """N-body with merging: Body {f32 x, f32 y, f32 vx, f32 vy, f32 m}, created
+    by one parallel_new on a fresh heap, so a body's creation index is its key
+    block*64 + slot."""
+
+    CLASSES = [[4, 4, 4, 4, 4]]
+
+    def __init__(self, seed=42, n=262144, G=1e-6, dt=1e-3, merge_dist=1e-4, hash_bits=21, pair_cap=4096,
+                 device="cuda", init=None):
+        self.n = n
+        M = (n + 63) // 64
+        self.heap = S.Heap(self.CLASSES, M, device=device)
+        arrs = inputs.nbody_initial(seed, n) if init is None else init
+        self.init = tuple(np.ascontiguousarray(a, dtype=np.float32) for a in arrs)
+        self._src = [_dev(a, device) for a in self.init]
+        self.head = torch.full((1 << hash_bits,), -1, dtype=torch.int32, device=device)
+        self.next = torch.empty(M * 64, dtype=torch.int32, device=device)
+        self.lab = torch.empty(M * 64, dtype=torch.int32, device=device)
+        self.merged = torch.zeros(M * 64, dtype=torch.uint8, device=device)
+        self.pairs = torch.empty(2 * pair_cap, dtype=torch.int32, device=device)
+        self.npairs = torch.zeros(1, dtype=torch.int32, device=device)
+        self.args = S.NbodyArgs(self.head.data_ptr(), self.next.data_ptr(), self.lab.data_ptr(),
+                                self.merged.data_ptr(), self.pairs.data_ptr(), self.npairs.data_ptr(),
+                                hash_bits, pair_cap, G, dt, merge_dist, 1024.0)
+
+    def populate(self, stream=None):
+        self.heap.parallel_new(0, self.n, S.CTOR_ARRAYS, S.ctor_arrays(self._src), stream=stream)
+
+    def phase(self, method, stream=None):
+        self.heap.parallel_do(0, method, self.args, stream=stream)
+
+    def merge(self, stream=None):
+        for m in S.NBODY_PHASES[:4]:
+            self.phase(m, stream)
+
+    def force_move(self, stream=None):
+        for m in S.NBODY_PHASES[4:]:
+            self.phase(m, stream)
+
+    def step(self, stream=None):
+        for m in S.NBODY_PHASES:
+            self.phase(m, stream)
+
+    def state(self):
+        """(ids, x, y, vx, vy, m) of the survivors in ascending id."""
+        x, y, vx, vy, m = self.heap.dump_objects(0, [np.float32] * 5)
+        refs = self.heap.dump_refs(0)
+        key = ((refs >> np.uint64(6)) & np.uint64((1 << 44) - 1)) * np.uint64(64) + (refs & np.uint64(63))
+        return key.astype(np.int32), x, y, vx, vy, m

@@ -181,3 +181,29 @@ def test_two_class_churn_type_changes(blocks, lineages, flags):
     assert st["block_init"] > 0
     if flags == 0:
         assert st["block_free"] > 0
+
+
+@pytest.mark.parametrize("drivers,blocks,lanes,iters,flags", [
+    (64 * 256, 256 + 16, 1, 200, 0),      # 256 waves, one allocation each, into 16 blocks
+    (64 * 256, 256 + 12, 1, 200, 1),      # same without rotation
+    (64 * 512, 512 + 40, 2, 100, 0),      # 512 waves, two lanes each (coalesced pairs)
+    (64 * 128, 128 + 8, 1, 300, 8),       # forced lookup failures: extra slow paths
+])
+def test_allocation_storm_forces_rollbacks(drivers, blocks, lanes, iters, flags):
+    """Many waves allocate and free in the same few blocks at once: blocks
+    empty, are invalidated and re-initialized to the other class while other
+    waves hold stale picks.  Afterwards nothing of either class is left, the
+    heap is consistent and no bounded retry gave up."""
+    say("storm", drivers, blocks, lanes, iters, flags)
+    smmo = S()
+    h = smmo.Heap([[4], [4], [4, 4]], blocks)         # drivers, class a (cap 64), class b (cap 32)
+    h.set_tuning(flags | smmo.TUNE_STATS, 5, 250000)
+    h.parallel_new(0, drivers, smmo.CTOR_ZERO)
+    h.parallel_do(0, smmo.M_STRESS, smmo.StressArgs(7, iters, lanes, 1, 2))
+    st = h.stats()
+    print("[stats]", st, flush=True)
+    s = check_heap(h, expect_live=[drivers, 0, 0])
+    assert s["free"] == blocks - drivers // 64
+    waves = drivers // 64
+    assert st["alloc_obj"] == st["free_obj"] == waves * lanes * iters
+    assert st["block_free"] > 0

@@ -1,0 +1,141 @@
+"""GPU parity of the n-body-with-merging workload (device_do all-pairs force,
+merge by connected components, destruction) against the CPU oracle.  FP32 is
+formed in the same order with one IEEE rounding per operation on both sides
+(-ffp-contract=off, correctly rounded / and sqrtf), so the comparison is
+bit-exact; the stated tolerance (relative 1e-5) is the fallback bar."""
+import numpy as np
+import pytest
+
+from helpers import check_heap, say
+from oracle import core
+from paper_1810_11765_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1810_11765_amd import smmo  # noqa: F401
+
+
+def W():
+    from paper_1810_11765_amd import workloads
+    return workloads
+
+
+def _inject(x, y, rng, k):
+    n = len(x)
+    for _ in range(k):
+        i, j = rng.choice(n, 2, replace=False)
+        x[j] = x[i] + np.float32(3e-5) * np.float32(rng.uniform(-1, 1))
+        y[j] = y[i] + np.float32(3e-5) * np.float32(rng.uniform(-1, 1))
+        if rng.random() < 0.3:                       # chain of three
+            l = rng.choice(n)
+            x[l] = x[j] + np.float32(7e-5); y[l] = y[j]
+
+
+def _same(gpu, ora, what):
+    for name, a, b in zip(("id", "x", "y", "vx", "vy", "m"), gpu, ora):
+        assert a.shape == b.shape, f"{what}: {name} count {a.shape} vs {b.shape}"
+        if name == "id":
+            assert np.array_equal(a, b), f"{what}: survivor ids differ"
+        else:
+            if not np.array_equal(a.view(np.uint32), b.view(np.uint32)):
+                rel = np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-30))
+                assert rel <= 1e-5, f"{what}: {name} rel err {rel}"
+
+
+@pytest.mark.parametrize("n,steps,seed", [(2048, 40, 1), (1000, 30, 2), (64 * 37 + 5, 10, 3)])
+def test_nbody_parity_small(n, steps, seed):
+    say("nbody small", n, steps)
+    rng = np.random.default_rng(seed)
+    x, y, vx, vy, m = inputs.nbody_initial(seed, n)
+    _inject(x, y, rng, 25)
+    sim = W().NBody(n=n, init=(x, y, vx, vy, m), G=1e-4)
+    sim.populate()
+    ora = (np.arange(n, dtype=np.int32), x, y, vx, vy, m)
+    total_pairs = 0
+    for s in range(steps):
+        sim.step()
+        ora, npairs = core.c4_step(*ora, G=1e-4)
+        total_pairs += npairs
+        if s in (0, steps - 1):
+            _same(sim.state(), ora, f"step {s + 1}")
+    assert total_pairs >= 25
+    check_heap(sim.heap, expect_live=[len(ora[0])])
+
+
+def test_nbody_full_size_sampled():
+    """262,144 bodies, one step: the merge phase against the oracle on the
+    whole state, the all-pairs force (device_do over 4,096 blocks) on sampled
+    bodies."""
+    say("nbody full")
+    n = 262144
+    sim = W().NBody(n=n)
+    sim.populate()
+    state = (np.arange(n, dtype=np.int32),) + sim.init
+    sim.merge()
+    merged, npairs = core.c4_merge_grid(*state)
+    _same(sim.state(), merged, "merge")
+    assert npairs > 100                                 # ~343 close pairs expected at this density
+    sim.force_move()
+    got = sim.state()
+    ids, x, y, vx, vy, m = merged
+    sel = np.sort(np.random.default_rng(0).choice(len(ids), 512, replace=False))
+    ax, ay = core.c4_accel(x, y, m, sel)
+    wvx = (vx[sel] + ax * np.float32(1e-3)).astype(np.float32)
+    wvy = (vy[sel] + ay * np.float32(1e-3)).astype(np.float32)
+    wx = (x[sel] + wvx * np.float32(1e-3)).astype(np.float32)
+    wy = (y[sel] + wvy * np.float32(1e-3)).astype(np.float32)
+    gsel = np.searchsorted(got[0], ids[sel])
+    assert np.array_equal(got[0][gsel], ids[sel])
+    for name, g, w in (("vx", got[3][gsel], wvx), ("vy", got[4][gsel], wvy), ("x", got[1][gsel], wx),
+                       ("y", got[2][gsel], wy), ("m", got[5][gsel], m[sel])):
+        if not np.array_equal(g.view(np.uint32), w.view(np.uint32)):
+            rel = np.max(np.abs(g - w) / np.maximum(np.abs(w), 1e-30))
+            assert rel <= 1e-5, f"{name} rel err {rel}"
+    check_heap(sim.heap, expect_live=[len(ids)])
+
+
+def test_nbody_full_size_properties():
+    """Properties that hold at any size after several full-size steps: no two
+    survivors closer than the merge distance after a merge phase, mass
+    conserved, every body finite."""
+    from scipy.spatial import cKDTree
+    say("nbody full properties")
+    sim = W().NBody(n=262144)
+    sim.populate()
+    m0 = float(sim.init[4].sum(dtype=np.float64))
+    for s in range(4):
+        sim.step()
+    sim.merge()
+    ids, x, y, vx, vy, m = sim.state()
+    assert np.isfinite(x).all() and np.isfinite(vx).all()
+    assert abs(float(m.sum(dtype=np.float64)) - m0) < 1e-3 * m0
+    pts = np.stack([x, y], 1).astype(np.float64)
+    for i, j in cKDTree(pts).query_pairs(r=1.2e-4):
+        dx, dy = np.float32(x[j] - x[i]), np.float32(y[j] - y[i])
+        assert np.sqrt(np.float32(dx * dx + dy * dy), dtype=np.float32) >= np.float32(1e-4)
+    check_heap(sim.heap, expect_live=[len(ids)])
+
+
+def test_correctly_rounded_div_sqrt_against_ieee():
+    """The FP32 `/` and sqrtf the kernels use are correctly rounded: the force
+    phase's interaction term on 2^24 random operand pairs equals the CPU's."""
+    say("div/sqrt")
+    rng = np.random.default_rng(5)
+    n = 1 << 12
+    x = rng.uniform(-1, 1, n).astype(np.float32)
+    y = rng.uniform(-1, 1, n).astype(np.float32)
+    m = np.exp(rng.standard_normal(n) * 2).astype(np.float32)
+    sim = W().NBody(n=n, init=(x, y, np.zeros(n, np.float32), np.zeros(n, np.float32), m), G=1.0, dt=1.0)
+    sim.populate()
+    sim.phase(34)                                      # FORCE only: v = a*1
+    _, _, _, vx, vy, _ = sim.state()
+    ax, ay = core.c4_accel(x, y, m, np.arange(n), G=1.0)
+    assert np.array_equal(vx.view(np.uint32), ax.view(np.uint32))
+    assert np.array_equal(vy.view(np.uint32), ay.view(np.uint32))

@@ -267,3 +267,29 @@ def test_nbody_step_against_double_precision_and_no_close_pairs():
     # after the merge phase no two survivors are closer than the threshold
     d = np.sqrt(d2 + np.eye(len(X0)))
     assert d.min() >= 1e-4 * 0.999
+
+
+def _inject_close_pairs(x, y, rng, k, chain=False):
+    """Put k bodies within 3e-5 of another body (and some 3-chains)."""
+    n = len(x)
+    for _ in range(k):
+        i, j = rng.choice(n, 2, replace=False)
+        x[j] = x[i] + np.float32(3e-5) * np.float32(rng.uniform(-1, 1))
+        y[j] = y[i] + np.float32(3e-5) * np.float32(rng.uniform(-1, 1))
+        if chain:
+            l = rng.choice(n)
+            x[l] = x[j] + np.float32(6e-5); y[l] = y[j]
+
+
+def test_grid_merge_equals_bruteforce_merge():
+    rng = np.random.default_rng(0)
+    n = 3000
+    x, y, vx, vy, m = inputs.nbody_initial(9, n)
+    vx = rng.standard_normal(n).astype(np.float32); vy = rng.standard_normal(n).astype(np.float32)
+    _inject_close_pairs(x, y, rng, 40, chain=True)
+    ids = np.arange(n, dtype=np.int32)
+    brute, nb = core.c4_step(ids, x, y, vx, vy, m, G=0.0, dt=0.0)      # G = dt = 0: merge only
+    grid, ng = core.c4_merge_grid(ids, x, y, vx, vy, m)
+    assert nb == ng and nb >= 40
+    for a, b in zip(brute, grid):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
