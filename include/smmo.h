@@ -129,6 +129,8 @@ enum smmo_counter {
 #define SMMO_TUNE_NO_COALESCE 2u    /* one slot per reservation ("-NoCoal") */
 #define SMMO_TUNE_STATS 4u          /* maintain device counters */
 #define SMMO_TUNE_FORCE_FAIL 8u     /* try_find_set fails force_fail_ppm / 1e6 of the time */
+#define SMMO_TUNE_SLOW_PICK 16u     /* pause ~20 us between picking an active block and
+                                       reserving in it (widens the race window of App. A.3) */
 
 /* -------------------------------------------------- heap management ---- */
 

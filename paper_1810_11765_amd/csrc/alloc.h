@@ -114,6 +114,8 @@ __device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t 
             bm_set(h, bm_active(h, cls), bid);
             count(h, SMMO_CNT_BLOCK_INIT);
         }
+        if (h.tune & SMMO_TUNE_SLOW_PICK)                 // fault injection: widen the pick/reserve window
+            for (int i = 0; i < 8; ++i) __builtin_amdgcn_s_sleep(127);
         // Block::reserve, coalesced: take up to `want` zero bits, rotated start
         uint64_t freeb = ~at_load(&h.alloc[bid]);
         if (!freeb) { count(h, SMMO_CNT_RESERVE_FAIL); continue; }

@@ -15,6 +15,15 @@
 
 using namespace smmo;
 
+// Launch shape of the streaming sweep: waves per CU (256 CUs) and groups of
+// four blocks in flight per wave.
+#ifndef SMMO_SWEEP_WAVES_PER_CU
+#define SMMO_SWEEP_WAVES_PER_CU 32
+#endif
+#ifndef SMMO_SWEEP_GROUPS
+#define SMMO_SWEEP_GROUPS 2
+#endif
+
 struct smmo_heap {
     smmo_raw_header hdr;   // host copy of the device header
     DevHeap dev;           // kernel-argument view
@@ -418,8 +427,9 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
                 heap->hdr.field_bytes[cls][a.fx] != 4 || heap->hdr.field_bytes[cls][a.fy] != 4)
                 return fail(SMMO_EINVAL, "axpy: fields must be 4-byte fields of the class");
             const uint64_t nwords = heap->hdr.level_words[0];
-            const uint64_t waves = std::min<uint64_t>(nwords, 256ull * 32);
-            k_doall_axpy<2><<<(unsigned)((waves + 3) / 4), kBlockThreads, 0, s>>>(heap->dev, cls, nwords, a);
+            const uint64_t waves = std::min<uint64_t>(nwords, 256ull * SMMO_SWEEP_WAVES_PER_CU);
+            k_doall_axpy<SMMO_SWEEP_GROUPS><<<(unsigned)((waves + 3) / 4), kBlockThreads, 0, s>>>(heap->dev, cls,
+                                                                                                nwords, a);
             LAUNCH_CHECK("k_doall_axpy");
             return SMMO_OK;
         }

@@ -324,3 +324,4 @@ M_STRESS = 5
 class StressArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("iters", C.c_uint32), ("lanes", C.c_uint32), ("cls_a", C.c_uint32),
                 ("cls_b", C.c_uint32)]
+TUNE_SLOW_PICK = 16

@@ -188,6 +188,7 @@ def test_two_class_churn_type_changes(blocks, lineages, flags):
     (64 * 256, 256 + 12, 1, 200, 1),      # same without rotation
     (64 * 512, 512 + 40, 2, 100, 0),      # 512 waves, two lanes each (coalesced pairs)
     (64 * 128, 128 + 8, 1, 300, 8),       # forced lookup failures: extra slow paths
+    (64 * 256, 256 + 10, 1, 60, 16),      # paused picks: blocks change type under a pick
 ])
 def test_allocation_storm_forces_rollbacks(drivers, blocks, lanes, iters, flags):
     """Many waves allocate and free in the same few blocks at once: blocks
@@ -207,3 +208,5 @@ def test_allocation_storm_forces_rollbacks(drivers, blocks, lanes, iters, flags)
     waves = drivers // 64
     assert st["alloc_obj"] == st["free_obj"] == waves * lanes * iters
     assert st["block_free"] > 0
+    if flags & 16:
+        assert st["type_rollback"] > 0        # the Alg. 1 rollback path really ran
