@@ -164,6 +164,39 @@ def sweep_sub(torch, nblocks):
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "status": h.status()}
 
 
+def batch_sub(torch, steps=200, count=256):
+    """Predator-prey instances of log-uniform side in [64, 1024): plain (one by
+    one, per-phase launches) vs batched (persistent kernel, graph replay) vs
+    served (Poisson arrivals at 50/s, continuous admission).  Results are
+    compared instance by instance between the three forms."""
+    import numpy as np
+    from paper_1810_11765_amd import serve as sv
+    from paper_1810_11765_amd import smmo as S
+    reqs = sv.make_requests(seed=42, count=count)
+    arena = S.Arena(sv.arena_bytes_for(reqs))
+    inst_steps = count * steps
+    plain, t_plain = sv.run_plain(reqs, steps, arena)
+    batched, t_batch, _ = sv.run_batched(reqs, steps, arena, per_launch=1, graph=True)
+    served = sv.serve(reqs, steps, arena, time_scale=1.0)
+    same = all(
+        all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], batched[r.rid][0])) and
+        all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], served["results"][r.rid][0]))
+        for r in reqs)
+    status = max([plain[r.rid][1] for r in reqs] + [batched[r.rid][1] for r in reqs] +
+                 [served["results"][r.rid][1] for r in reqs])
+    lat = served["latency_ms"]
+    return {"instances": count, "steps": steps, "cells_total": int(sum(r.side * r.side for r in reqs)),
+            "plain_steps_s": round(inst_steps / t_plain, 1),
+            "batched_graph_steps_s": round(inst_steps / t_batch, 1),
+            "batched_over_plain": round(t_plain / t_batch, 2),
+            "served_wall_s": round(served["wall_s"], 3), "served_busy_s": round(served["busy_s"], 3),
+            "served_steps_s": round(inst_steps / served["wall_s"], 1),
+            "served_p50_step_ms": round(float(np.percentile(lat, 50)), 4),
+            "served_p99_step_ms": round(float(np.percentile(lat, 99)), 4),
+            "served_max_admit_delay_s": round(float(served["admit_delay_s"].max()), 4),
+            "identical_results": bool(same), "status": int(status)}
+
+
 def cpu_baseline():
     """The CPU oracle's Life run (single thread) on whole 200-step runs of the
     same 512 x 512 workload, repeated until about 10 s of CPU time."""
@@ -216,6 +249,7 @@ def main():
     if not args.no_sub:
         out["alloc_microbench"] = alloc_sub(torch, workloads)
         out["sweep"] = sweep_sub(torch, args.sweep_blocks)
+        out["predator_prey_plain_vs_batched"] = batch_sub(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

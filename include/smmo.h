@@ -358,6 +358,45 @@ int smmo_clear_status(smmo_heap* heap, void* stream);
 /* Copy `n` (<= SMMO_CNT_NUM) device counters to host.  Synchronizes. */
 int smmo_stats(smmo_heap* heap, uint64_t* out, uint32_t n, void* stream);
 
+/* ---------------------------------------------------- arena and batch ---- */
+/* An arena is a host-side range allocator over one caller device buffer
+ * (256-B granules, first fit); it lets many heaps and their workload arrays
+ * live in one allocation and be admitted and released at run time.  It never
+ * touches device memory itself. */
+typedef struct smmo_arena smmo_arena;
+int smmo_arena_create(void* dev_mem, uint64_t bytes, smmo_arena** out);
+int smmo_arena_destroy(smmo_arena* arena);
+/* *dev_out = a 256-B aligned range of `bytes`; SMMO_ENOMEM_DEVICE if no
+ * free range is large enough. */
+int smmo_arena_alloc(smmo_arena* arena, uint64_t bytes, void** dev_out);
+int smmo_arena_free(smmo_arena* arena, void* dev_ptr);
+int smmo_arena_stats(const smmo_arena* arena, uint64_t* free_bytes, uint64_t* largest_free);
+
+/* A batch advances many independent predator-prey instances (each its own
+ * heap and grids, see smmo_wator_args) with ONE persistent kernel launch per
+ * call: each instance gets a share of the workgroups proportional to its
+ * grid, and its four phases per step are separated by barriers among its own
+ * workgroups only.  The batch's device tables live in `arena`. */
+typedef struct smmo_batch smmo_batch;
+int smmo_batch_create(smmo_arena* arena, uint32_t max_instances, smmo_batch** out);
+int smmo_batch_destroy(smmo_batch* batch);     /* returns its tables to the arena */
+/* Add an instance that runs `steps` more steps; args.step is ignored (the
+ * batch counts steps from 1).  `heap` must outlive the instance.
+ * Synchronizes the stream.  *slot_out identifies the instance. */
+int smmo_batch_add_wator(smmo_batch* batch, smmo_heap* heap, const smmo_wator_args* args, uint32_t steps,
+                         void* stream, uint32_t* slot_out);
+int smmo_batch_remove(smmo_batch* batch, uint32_t slot);
+/* Advance every instance by min(steps, its remaining steps).  Asynchronous,
+ * no host synchronization and no memset (safe under stream capture) unless
+ * the instance set changed since the last call, in which case the schedule
+ * is uploaded first (synchronously). */
+int smmo_batch_step(smmo_batch* batch, uint32_t steps, void* stream);
+/* Remaining steps of every slot (0xFFFFFFFF for an empty slot), to host
+ * memory of max_instances entries.  Synchronizes. */
+int smmo_batch_remaining(smmo_batch* batch, uint32_t* out, void* stream);
+/* Workgroups of the persistent kernel (the occupancy-bounded grid). */
+int smmo_batch_grid(const smmo_batch* batch, uint32_t* workgroups);
+
 /* Handle layout: bits 56-63 class id + 1, bits 6-49 block, bits 0-5 slot;
  * 0 is the null handle.  Host-side helpers. */
 uint64_t smmo_ref_make(uint32_t cls, uint64_t block, uint32_t slot);

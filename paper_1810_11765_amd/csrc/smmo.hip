@@ -10,8 +10,11 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "methods.h"
 #include "nbody.h"
+
+#include <map>
 
 using namespace smmo;
 
@@ -578,6 +581,237 @@ int smmo_stats(smmo_heap* heap, uint64_t* out, uint32_t n, void* stream) {
     hipStream_t s = S(stream);
     HIP_TRY(hipMemcpyAsync(out, heap->dev.counters, 8ull * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return SMMO_OK;
+}
+
+// ------------------------------------------------------------- arena ----
+}  // extern "C"
+
+struct smmo_arena {
+    uint8_t* base;
+    uint64_t bytes;
+    std::map<uint64_t, uint64_t> free_ranges;   // offset -> size
+    std::map<uint64_t, uint64_t> used;          // offset -> size
+};
+
+struct smmo_batch {
+    smmo_arena* arena;
+    uint32_t max_inst;
+    uint32_t grid;                              // persistent workgroups
+    uint8_t* dev;                               // device tables (from the arena)
+    BatchDesc* d_desc;
+    BatchProg* d_prog;
+    BatchSched* d_sched;
+    int32_t* d_wg_inst;
+    uint32_t* d_bar;
+    std::vector<int> used;                      // slot in use
+    std::vector<uint64_t> weight;               // grid cells of each slot
+    bool dirty;
+};
+
+extern "C" {
+
+int smmo_arena_create(void* dev_mem, uint64_t bytes, smmo_arena** out) {
+    if (!dev_mem || !out || bytes < 256) return fail(SMMO_EINVAL, "arena: bad arguments");
+    smmo_arena* A = new smmo_arena();
+    uint64_t skew = (256 - reinterpret_cast<uintptr_t>(dev_mem) % 256) % 256;
+    A->base = static_cast<uint8_t*>(dev_mem) + skew;
+    A->bytes = (bytes - skew) / 256 * 256;
+    A->free_ranges[0] = A->bytes;
+    *out = A;
+    return SMMO_OK;
+}
+
+int smmo_arena_destroy(smmo_arena* arena) {
+    delete arena;
+    return SMMO_OK;
+}
+
+int smmo_arena_alloc(smmo_arena* A, uint64_t bytes, void** dev_out) {
+    if (!A || !dev_out || bytes == 0) return fail(SMMO_EINVAL, "arena_alloc: bad arguments");
+    const uint64_t need = align_up(bytes, 256);
+    for (auto it = A->free_ranges.begin(); it != A->free_ranges.end(); ++it) {
+        if (it->second < need) continue;
+        const uint64_t off = it->first, size = it->second;
+        A->free_ranges.erase(it);
+        if (size > need) A->free_ranges[off + need] = size - need;
+        A->used[off] = need;
+        *dev_out = A->base + off;
+        return SMMO_OK;
+    }
+    return fail(SMMO_ENOMEM_DEVICE, "arena: no free range of %llu bytes", (unsigned long long)need);
+}
+
+int smmo_arena_free(smmo_arena* A, void* dev_ptr) {
+    if (!A || !dev_ptr) return fail(SMMO_EINVAL, "arena_free: bad arguments");
+    const uint64_t off = static_cast<uint8_t*>(dev_ptr) - A->base;
+    auto u = A->used.find(off);
+    if (u == A->used.end()) return fail(SMMO_EINVAL, "arena_free: pointer was not allocated here");
+    uint64_t start = off, size = u->second;
+    A->used.erase(u);
+    auto next = A->free_ranges.lower_bound(start);
+    if (next != A->free_ranges.end() && next->first == start + size) {   // merge with the next range
+        size += next->second;
+        A->free_ranges.erase(next);
+    }
+    auto prev = A->free_ranges.lower_bound(start);
+    if (prev != A->free_ranges.begin()) {
+        --prev;
+        if (prev->first + prev->second == start) {                         // merge with the previous
+            start = prev->first;
+            size += prev->second;
+            A->free_ranges.erase(prev);
+        }
+    }
+    A->free_ranges[start] = size;
+    return SMMO_OK;
+}
+
+int smmo_arena_stats(const smmo_arena* A, uint64_t* free_bytes, uint64_t* largest_free) {
+    if (!A) return fail(SMMO_EINVAL, "null arena");
+    uint64_t tot = 0, big = 0;
+    for (auto& kv : A->free_ranges) {
+        tot += kv.second;
+        big = std::max(big, kv.second);
+    }
+    if (free_bytes) *free_bytes = tot;
+    if (largest_free) *largest_free = big;
+    return SMMO_OK;
+}
+
+// ------------------------------------------------------------- batch ----
+int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
+    if (!arena || !out || max_inst == 0 || max_inst > 65536) return fail(SMMO_EINVAL, "batch: bad arguments");
+    int dev = 0, cus = 0, per_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_wator, 256, 0));
+    if (per_cu < 1) return fail(SMMO_EHIP, "batch kernel cannot be resident");
+    smmo_batch* B = new smmo_batch();
+    B->arena = arena;
+    B->max_inst = max_inst;
+    // every workgroup must be resident at once for the instance barriers;
+    // stay at half the reported occupancy for margin
+    B->grid = (uint32_t)cus * (uint32_t)std::max(1, std::min(per_cu / 2, 4));
+    const uint64_t bytes = align_up(sizeof(BatchDesc) * max_inst, 256) + align_up(sizeof(BatchProg) * max_inst, 256) +
+                           align_up(sizeof(BatchSched) * max_inst, 256) + align_up(4ull * B->grid, 256) +
+                           align_up(4ull * max_inst, 256);
+    void* p = nullptr;
+    int rc = smmo_arena_alloc(arena, bytes, &p);
+    if (rc) { delete B; return rc; }
+    uint8_t* q = static_cast<uint8_t*>(p);
+    B->dev = q;
+    B->d_desc = reinterpret_cast<BatchDesc*>(q);        q += align_up(sizeof(BatchDesc) * max_inst, 256);
+    B->d_prog = reinterpret_cast<BatchProg*>(q);        q += align_up(sizeof(BatchProg) * max_inst, 256);
+    B->d_sched = reinterpret_cast<BatchSched*>(q);      q += align_up(sizeof(BatchSched) * max_inst, 256);
+    B->d_wg_inst = reinterpret_cast<int32_t*>(q);       q += align_up(4ull * B->grid, 256);
+    B->d_bar = reinterpret_cast<uint32_t*>(q);
+    B->used.assign(max_inst, 0);
+    B->weight.assign(max_inst, 0);
+    B->dirty = true;
+    std::vector<BatchProg> prog(max_inst, BatchProg{0, 0});
+    HIP_TRY(hipMemcpy(B->d_prog, prog.data(), sizeof(BatchProg) * max_inst, hipMemcpyHostToDevice));
+    *out = B;
+    return SMMO_OK;
+}
+
+int smmo_batch_destroy(smmo_batch* B) {
+    if (!B) return SMMO_OK;
+    smmo_arena_free(B->arena, B->dev);
+    delete B;
+    return SMMO_OK;
+}
+
+int smmo_batch_add_wator(smmo_batch* B, smmo_heap* heap, const smmo_wator_args* args, uint32_t steps,
+                         void* stream, uint32_t* slot_out) {
+    if (!B || !heap || !args || !slot_out) return fail(SMMO_EINVAL, "batch_add: null argument");
+    if (args->fish_cls >= heap->hdr.ncls || args->shark_cls >= heap->hdr.ncls)
+        return fail(SMMO_EINVAL, "batch_add: class out of range");
+    uint32_t slot = 0;
+    while (slot < B->max_inst && B->used[slot]) ++slot;
+    if (slot == B->max_inst) return fail(SMMO_ENOMEM_DEVICE, "batch_add: all %u slots in use", B->max_inst);
+    BatchDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.h = heap->dev;
+    d.a = *args;
+    d.a.step = 0;
+    BatchProg pr{steps, 0};
+    hipStream_t s = S(stream);
+    HIP_TRY(hipMemcpyAsync(&B->d_desc[slot], &d, sizeof d, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(&B->d_prog[slot], &pr, sizeof pr, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    B->used[slot] = 1;
+    B->weight[slot] = (uint64_t)args->width * (uint64_t)args->height;
+    B->dirty = true;
+    *slot_out = slot;
+    return SMMO_OK;
+}
+
+int smmo_batch_remove(smmo_batch* B, uint32_t slot) {
+    if (!B || slot >= B->max_inst || !B->used[slot]) return fail(SMMO_EINVAL, "batch_remove: bad slot");
+    B->used[slot] = 0;
+    B->weight[slot] = 0;
+    B->dirty = true;
+    return SMMO_OK;
+}
+
+// Workgroups per instance proportional to its cells (at least one each).
+static int batch_schedule(smmo_batch* B, hipStream_t s) {
+    std::vector<int32_t> wg(B->grid, -1);
+    std::vector<BatchSched> sched(B->max_inst, BatchSched{0, 0});
+    uint64_t total = 0;
+    uint32_t n = 0;
+    for (uint32_t i = 0; i < B->max_inst; ++i)
+        if (B->used[i]) { total += B->weight[i]; ++n; }
+    if (n > B->grid) return fail(SMMO_EINVAL, "batch: %u instances but only %u workgroups", n, B->grid);
+    uint32_t next = 0;
+    uint32_t spare = B->grid - n;                          // beyond one each
+    for (uint32_t i = 0; i < B->max_inst; ++i) {
+        if (!B->used[i]) continue;
+        uint32_t extra = total ? (uint32_t)((double)spare * (double)B->weight[i] / (double)total) : 0;
+        // cap by the instance's size: one workgroup per 4 L0 units is plenty
+        uint32_t cnt = 1 + extra;
+        sched[i] = BatchSched{next, cnt};
+        for (uint32_t k = 0; k < cnt; ++k) wg[next + k] = (int32_t)i;
+        next += cnt;
+    }
+    HIP_TRY(hipMemcpy(B->d_sched, sched.data(), sizeof(BatchSched) * B->max_inst, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(B->d_wg_inst, wg.data(), 4ull * B->grid, hipMemcpyHostToDevice));
+    (void)s;
+    B->dirty = false;
+    return SMMO_OK;
+}
+
+int smmo_batch_step(smmo_batch* B, uint32_t steps, void* stream) {
+    if (!B) return fail(SMMO_EINVAL, "null batch");
+    if (steps == 0) return SMMO_OK;
+    hipStream_t s = S(stream);
+    if (B->dirty) {
+        HIP_TRY(hipStreamSynchronize(s));
+        int rc = batch_schedule(B, s);
+        if (rc) return rc;
+    }
+    k_fill_u64<<<grid_for((B->max_inst + 1) / 2, 256), 256, 0, s>>>(reinterpret_cast<unsigned long long*>(B->d_bar),
+                                                                     (B->max_inst + 1) / 2, 0);
+    LAUNCH_CHECK("k_fill_u64");
+    k_batch_wator<<<B->grid, 256, 0, s>>>(B->d_desc, B->d_prog, B->d_sched, B->d_wg_inst, B->d_bar, steps);
+    LAUNCH_CHECK("k_batch_wator");
+    return SMMO_OK;
+}
+
+int smmo_batch_remaining(smmo_batch* B, uint32_t* out, void* stream) {
+    if (!B || !out) return fail(SMMO_EINVAL, "null argument");
+    std::vector<BatchProg> prog(B->max_inst);
+    hipStream_t s = S(stream);
+    HIP_TRY(hipMemcpyAsync(prog.data(), B->d_prog, sizeof(BatchProg) * B->max_inst, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < B->max_inst; ++i) out[i] = B->used[i] ? prog[i].remaining : 0xFFFFFFFFu;
+    return SMMO_OK;
+}
+
+int smmo_batch_grid(const smmo_batch* B, uint32_t* workgroups) {
+    if (!B || !workgroups) return fail(SMMO_EINVAL, "null argument");
+    *workgroups = B->grid;
     return SMMO_OK;
 }
 

@@ -1,0 +1,188 @@
+"""Batched and served predator-prey instances.
+
+Three ways to advance a set of independent instances (each its own heap and
+grids carved from one arena):
+
+* plain      one instance after the other through the per-phase C-ABI calls
+             (four do-alls and two snapshots per step, one launch each);
+* batched    all instances admitted up front, every step one persistent
+             kernel launch for all of them (smmo_batch_step), optionally
+             replayed from a captured HIP graph;
+* served     continuous batching: requests arrive over time (Poisson), are
+             admitted between steps when the arena has room for their heap
+             and grids, advance together with whatever else is running, and
+             leave when done; per instance-step latency is recorded.
+
+Only orchestration lives here; every object operation runs in libsmmo.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import inputs
+from . import smmo as S
+from .workloads import WaTor, wator_blocks
+
+
+@dataclass
+class Request:
+    rid: int
+    side: int
+    seed: int
+    arrival: float
+    kind0: np.ndarray = field(repr=False, default=None)
+
+
+def make_requests(seed: int = 42, count: int = 256, rate: float = 50.0, lo: int = 64, hi: int = 1024):
+    sides, seeds, arrivals = inputs.serving_instances(seed, count, rate, lo, hi)
+    out = []
+    for i in range(count):
+        s = int(sides[i])
+        out.append(Request(i, s, int(seeds[i]), float(arrivals[i]), inputs.wator_initial(int(seeds[i]), s, s)))
+    return out
+
+
+def arena_bytes_for(reqs) -> int:
+    """Arena size that holds every request at once (plus batch tables)."""
+    tot = 1 << 22
+    for r in reqs:
+        n = r.side * r.side
+        tot += S.heap_bytes(WaTor.CLASSES, wator_blocks(r.kind0)) + 16 * n + 4096
+    return tot
+
+
+def instance_state(w: WaTor):
+    """(kind, age, energy) per cell of a finished instance."""
+    return w.state()
+
+
+class Fleet:
+    """A batch plus the instances it runs."""
+
+    def __init__(self, arena: S.Arena, max_instances: int = 256):
+        self.arena = arena
+        self.batch = S.Batch(arena, max_instances)
+        self.live = {}                      # slot -> (request, WaTor)
+
+    def admit(self, req: Request, steps: int, stream=None) -> bool:
+        try:
+            w = WaTor(seed=req.seed, width=req.side, height=req.side, num_blocks=None, kind0=req.kind0,
+                      arena=self.arena)
+        except S.SmmoError:
+            return False                    # no room in the arena yet
+        w.populate(stream)
+        slot = self.batch.add(w.heap, w.args, steps, stream)
+        self.live[slot] = (req, w)
+        return True
+
+    def harvest(self, stream=None):
+        """Finished instances: (request, state, status); their memory is released."""
+        done = []
+        rem = self.batch.remaining(stream)
+        for slot in [s for s in self.live if rem[s] == 0]:
+            req, w = self.live.pop(slot)
+            done.append((req, instance_state(w), w.heap.status()))
+            self.batch.remove(slot)
+            w.release()
+        return done
+
+    def close(self):
+        for req, w in self.live.values():
+            w.release()
+        self.live.clear()
+        self.batch.close()
+
+
+def run_plain(reqs, steps: int, arena: S.Arena):
+    """One instance at a time, per-phase launches.  Returns (results, seconds)."""
+    results = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        w = WaTor(seed=r.seed, width=r.side, height=r.side, num_blocks=None, kind0=r.kind0, arena=arena)
+        w.populate()
+        for _ in range(steps):
+            w.step()
+        results[r.rid] = (instance_state(w), w.heap.status())
+        w.release()
+    torch.cuda.synchronize()
+    return results, time.perf_counter() - t0
+
+
+def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bool = False):
+    """All instances admitted, then `steps` steps of the persistent kernel.
+    Returns (results, seconds of the stepping, grid workgroups)."""
+    fleet = Fleet(arena, max(len(reqs), 1))
+    for r in reqs:
+        assert fleet.admit(r, steps), "arena too small for the whole batch"
+    torch.cuda.synchronize()
+    launches = (steps + per_launch - 1) // per_launch
+    if graph:
+        fleet.batch.step(per_launch)          # uploads the schedule outside capture
+        torch.cuda.synchronize()
+        launches -= 1
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(launches):
+                    fleet.batch.step(per_launch, stream=s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    else:
+        t0 = time.perf_counter()
+        for _ in range(launches):
+            fleet.batch.step(per_launch)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    results = {req.rid: (st, status) for req, st, status in fleet.harvest()}
+    assert not fleet.live, "instances left unfinished"
+    fleet.close()
+    return results, dt, None
+
+
+def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instances: int = 256):
+    """Continuous batching over arrivals (arrival times scaled by time_scale).
+
+    Returns dict with results per request, per instance-step latencies (ms),
+    wall seconds, busy seconds and admission delays.
+    """
+    fleet = Fleet(arena, max_instances)
+    pending = deque(sorted(reqs, key=lambda r: r.arrival))
+    lat, admit_delay, results = [], [], {}
+    busy = 0.0
+    t0 = time.perf_counter()
+    while pending or fleet.live:
+        now = time.perf_counter() - t0
+        while pending and pending[0].arrival * time_scale <= now:
+            if not fleet.admit(pending[0], steps):
+                if not fleet.live:
+                    raise S.SmmoError(f"request {pending[0].rid} does not fit in the empty arena")
+                break                                   # wait until memory frees up
+            admit_delay.append(now - pending[0].arrival * time_scale)
+            pending.popleft()
+        if fleet.live:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fleet.batch.step(1)
+            b.record()
+            b.synchronize()
+            ms = a.elapsed_time(b)
+            busy += ms * 1e-3
+            lat.extend([ms] * len(fleet.live))
+            for req, st, status in fleet.harvest():
+                results[req.rid] = (st, status)
+        elif pending:
+            time.sleep(max(0.0, pending[0].arrival * time_scale - (time.perf_counter() - t0)))
+    wall = time.perf_counter() - t0
+    fleet.close()
+    return {"results": results, "latency_ms": np.array(lat), "wall_s": wall, "busy_s": busy,
+            "admit_delay_s": np.array(admit_delay)}

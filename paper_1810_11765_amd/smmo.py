@@ -185,16 +185,19 @@ class Heap:
     """A heap of `num_blocks` blocks for `classes` (lists of field byte sizes)
     inside one torch uint8 device tensor owned by this object."""
 
-    def __init__(self, classes, num_blocks: int, device="cuda", stream=None):
+    def __init__(self, classes, num_blocks: int, device="cuda", stream=None, dev_ptr: int | None = None):
         import torch
         self.classes = [list(c) for c in classes]
         self.num_blocks = num_blocks
         nbytes = heap_bytes(self.classes, num_blocks)
-        # 4 KiB slack so the buffer can be aligned to 256 bytes
-        self.buf = torch.empty(nbytes + 4096, dtype=torch.uint8, device=device)
-        base = self.buf.data_ptr()
-        self.offset = (-base) % 256
-        self.base = base + self.offset
+        if dev_ptr is None:
+            # 4 KiB slack so the buffer can be aligned to 256 bytes
+            self.buf = torch.empty(nbytes + 4096, dtype=torch.uint8, device=device)
+            base = self.buf.data_ptr()
+            self.base = base + (-base) % 256
+        else:
+            self.buf = None                      # memory owned by the caller (an arena range)
+            self.base = dev_ptr
         self.nbytes = nbytes
         descs, _keep = _descs(self.classes)
         h = C.c_void_p()
@@ -325,3 +328,101 @@ class StressArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("iters", C.c_uint32), ("lanes", C.c_uint32), ("cls_a", C.c_uint32),
                 ("cls_b", C.c_uint32)]
 TUNE_SLOW_PICK = 16
+
+
+def _bind_batch():
+    L = lib()
+    P, u32, u64, i = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+    sig = {
+        "smmo_arena_create": ([P, u64, P], i), "smmo_arena_destroy": ([P], i),
+        "smmo_arena_alloc": ([P, u64, P], i), "smmo_arena_free": ([P, P], i),
+        "smmo_arena_stats": ([P, P, P], i),
+        "smmo_batch_create": ([P, u32, P], i), "smmo_batch_destroy": ([P], i),
+        "smmo_batch_add_wator": ([P, P, P, u32, P, P], i), "smmo_batch_remove": ([P, u32], i),
+        "smmo_batch_step": ([P, u32, P], i), "smmo_batch_remaining": ([P, P, P], i),
+        "smmo_batch_grid": ([P, P], i),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+class Arena:
+    """Range allocator (in the library) over one torch device buffer."""
+
+    def __init__(self, nbytes: int, device="cuda"):
+        import torch
+        L = _bind_batch()
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        check(L.smmo_arena_create(C.c_void_p(self.buf.data_ptr()), nbytes + 256, C.byref(h)))
+        self.h = h
+
+    def alloc(self, nbytes: int) -> int:
+        p = C.c_void_p()
+        check(lib().smmo_arena_alloc(self.h, nbytes, C.byref(p)))
+        return p.value
+
+    def try_alloc(self, nbytes: int):
+        p = C.c_void_p()
+        rc = lib().smmo_arena_alloc(self.h, nbytes, C.byref(p))
+        return p.value if rc == 0 else None
+
+    def free(self, ptr: int) -> None:
+        check(lib().smmo_arena_free(self.h, C.c_void_p(ptr)))
+
+    def stats(self):
+        f, big = C.c_uint64(), C.c_uint64()
+        check(lib().smmo_arena_stats(self.h, C.byref(f), C.byref(big)))
+        return f.value, big.value
+
+    def view(self, ptr: int, count: int, dtype):
+        """torch view of `count` elements of `dtype` at device address ptr."""
+        import torch
+        off = ptr - self.buf.data_ptr()
+        nbytes = count * torch.empty((), dtype=dtype).element_size()
+        return self.buf[off: off + nbytes].view(dtype)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().smmo_arena_destroy(self.h)
+            self.h = None
+
+
+class Batch:
+    """Persistent-kernel batch of predator-prey instances (see smmo.h)."""
+
+    def __init__(self, arena: Arena, max_instances: int = 256):
+        L = _bind_batch()
+        h = C.c_void_p()
+        check(L.smmo_batch_create(arena.h, max_instances, C.byref(h)))
+        self.h = h
+        self.max_instances = max_instances
+
+    def add(self, heap, args: "WatorArgs", steps: int, stream=None) -> int:
+        slot = C.c_uint32()
+        check(lib().smmo_batch_add_wator(self.h, heap.h, C.byref(args), steps, _stream(stream), C.byref(slot)))
+        return slot.value
+
+    def remove(self, slot: int) -> None:
+        check(lib().smmo_batch_remove(self.h, slot))
+
+    def step(self, steps: int = 1, stream=None) -> None:
+        check(lib().smmo_batch_step(self.h, steps, _stream(stream)))
+
+    def remaining(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.max_instances, dtype=np.uint32)
+        check(lib().smmo_batch_remaining(self.h, out.ctypes.data, _stream(stream)))
+        return out
+
+    def grid(self) -> int:
+        g = C.c_uint32()
+        check(lib().smmo_batch_grid(self.h, C.byref(g)))
+        return g.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().smmo_batch_destroy(self.h)
+            self.h = None

@@ -105,6 +105,15 @@ class LifeGrid:
         return alive, ages
 
 
+def wator_blocks(kind0: np.ndarray) -> int:
+    """Heap blocks for a predator-prey instance: 4.5x the blocks its initial
+    fish (64 per block) and sharks (42 per block) fill, plus 16.  The oracle
+    shows the population peaking at up to ~3.15x its initial size under these
+    rules, so the 2x of a plain reading would run out of blocks."""
+    nf, ns = int((kind0 == 1).sum()), int((kind0 == 2).sum())
+    return int(4.5 * (-(-nf // 64) + -(-ns // 42))) + 16
+
+
 class WaTor:
     """Predator-prey grid: Fish {int32 pos, int32 age} (class 0) and Shark
     {int32 pos, int32 age, int32 energy} (class 1) on a width x height torus."""
@@ -114,15 +123,32 @@ class WaTor:
 
     def __init__(self, seed=42, width=1024, height=1024, num_blocks=32768, fish=0.20, shark=0.05,
                  fish_breed=3, shark_breed=8, eat_gain=4, shark_e0=4, device="cuda",
-                 kind0: np.ndarray | None = None):
+                 kind0: np.ndarray | None = None, arena: "S.Arena | None" = None):
         self.seed, self.W, self.H = seed, width, height
         self.params = dict(fish_breed=fish_breed, shark_breed=shark_breed, eat_gain=eat_gain, shark_e0=shark_e0)
-        self.heap = S.Heap(self.CLASSES, num_blocks, device=device)
         n = width * height
         self.kind0 = inputs.wator_initial(seed, width, height, fish, shark) if kind0 is None else kind0
-        self.occ = torch.zeros(n, dtype=torch.int64, device=device)
-        self.claim = torch.full((n,), INT32_MAX, dtype=torch.int32, device=device)
-        self.want = torch.zeros(n, dtype=torch.int32, device=device)
+        self.arena, self.region = arena, None
+        if num_blocks is None:
+            num_blocks = wator_blocks(self.kind0)
+        if arena is None:
+            self.heap = S.Heap(self.CLASSES, num_blocks, device=device)
+            self.occ = torch.zeros(n, dtype=torch.int64, device=device)
+            self.claim = torch.full((n,), INT32_MAX, dtype=torch.int32, device=device)
+            self.want = torch.zeros(n, dtype=torch.int32, device=device)
+        else:
+            # one arena range: heap, then the three grids
+            hb = (S.heap_bytes(self.CLASSES, num_blocks) + 255) // 256 * 256
+            gb = (8 * n + 255) // 256 * 256 + 2 * ((4 * n + 255) // 256 * 256)
+            self.region = arena.alloc(hb + gb)
+            self.heap = S.Heap(self.CLASSES, num_blocks, dev_ptr=self.region)
+            p = self.region + hb
+            self.occ = arena.view(p, n, torch.int64); p += (8 * n + 255) // 256 * 256
+            self.claim = arena.view(p, n, torch.int32); p += (4 * n + 255) // 256 * 256
+            self.want = arena.view(p, n, torch.int32)
+            self.occ.zero_()
+            self.claim.fill_(INT32_MAX)
+        self.num_blocks = num_blocks
         fpos = np.nonzero(self.kind0 == 1)[0].astype(np.int32)
         spos = np.nonzero(self.kind0 == 2)[0].astype(np.int32)
         self._f = [_dev(fpos, device), None]
@@ -132,6 +158,13 @@ class WaTor:
                                 seed & (2**64 - 1), width, height, 0, fish_breed, shark_breed, eat_gain,
                                 shark_e0, self.FISH, self.SHARK, 0)
         self.t = 0
+
+    def release(self):
+        """Give an arena-backed instance's memory back to the arena."""
+        self.heap.close()
+        if self.region is not None:
+            self.arena.free(self.region)
+            self.region = None
 
     def populate(self, stream=None):
         if self.nf0:

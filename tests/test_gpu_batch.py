@@ -1,0 +1,87 @@
+"""GPU parity of the batched and served predator-prey forms: every instance's
+result is the oracle's for its own size and seed, alone or in the mix, with
+the persistent batch kernel, graph replay and continuous admission."""
+import numpy as np
+import pytest
+
+from helpers import say
+from oracle import core
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1810_11765_amd import smmo  # noqa: F401
+
+
+def SV():
+    from paper_1810_11765_amd import serve
+    return serve
+
+
+def S():
+    from paper_1810_11765_amd import smmo
+    return smmo
+
+
+def _check(results, reqs, steps):
+    assert sorted(results) == sorted(r.rid for r in reqs)
+    for r in reqs:
+        (kind, age, energy), status = results[r.rid]
+        assert status == 0, f"request {r.rid}: device status {status:#x}"
+        ok, oa, oe = core.c3_run(r.kind0, r.side, r.side, r.seed, steps)
+        assert np.array_equal(kind, ok), f"request {r.rid} (side {r.side}): occupancy differs"
+        assert np.array_equal(age[kind > 0], oa[ok > 0]), f"request {r.rid}: ages differ"
+        assert np.array_equal(energy[kind == 2], oe[ok == 2]), f"request {r.rid}: energies differ"
+
+
+@pytest.mark.parametrize("per_launch,graph", [(1, False), (7, False), (1, True), (10, True)])
+def test_batched_instances_match_oracle(per_launch, graph):
+    say("batched", per_launch, graph)
+    sv = SV()
+    reqs = sv.make_requests(seed=5, count=12, lo=12, hi=100)
+    arena = S().Arena(sv.arena_bytes_for(reqs))
+    results, dt, _ = sv.run_batched(reqs, 40, arena, per_launch=per_launch, graph=graph)
+    _check(results, reqs, 40)
+    free, largest = arena.stats()
+    assert free == largest                                   # every range returned and merged
+
+
+def test_plain_one_by_one_matches_oracle():
+    say("plain")
+    sv = SV()
+    reqs = sv.make_requests(seed=6, count=6, lo=12, hi=80)
+    arena = S().Arena(sv.arena_bytes_for(reqs))
+    results, dt = sv.run_plain(reqs, 30, arena)
+    _check(results, reqs, 30)
+
+
+def test_serving_continuous_admission_matches_oracle():
+    """Requests arrive while others run (arrivals compressed 20x); each result
+    equals the oracle's for the instance alone."""
+    say("serve")
+    sv = SV()
+    reqs = sv.make_requests(seed=8, count=16, lo=16, hi=128)
+    arena = S().Arena(sv.arena_bytes_for(reqs))
+    out = sv.serve(reqs, 30, arena, time_scale=0.05)
+    _check(out["results"], reqs, 30)
+    assert len(out["latency_ms"]) == 16 * 30                # every instance-step timed
+    assert out["latency_ms"].min() > 0
+
+
+def test_serving_waits_for_memory():
+    """An arena that holds only a few instances at once: later requests wait
+    for earlier ones to leave, and all results still match."""
+    say("serve small arena")
+    sv = SV()
+    reqs = sv.make_requests(seed=9, count=10, lo=40, hi=64)
+    need = sv.arena_bytes_for(reqs)
+    arena = S().Arena(need // 3)
+    out = sv.serve(reqs, 20, arena, time_scale=0.0)         # all arrive at once
+    _check(out["results"], reqs, 20)
+    assert len(out["admit_delay_s"]) == 10 and out["admit_delay_s"].max() > 0

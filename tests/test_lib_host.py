@@ -94,3 +94,30 @@ def test_strerror_codes():
     L = S.lib()
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.smmo_strerror(code)
+
+
+def test_arena_first_fit_and_merging():
+    """The arena is host-side bookkeeping over a device range: exercise it on
+    a fake base address (no device access happens)."""
+    L = S._bind_batch()
+    base = 0x7f0000000000
+    h = C.c_void_p()
+    assert L.smmo_arena_create(C.c_void_p(base), 1 << 20, C.byref(h)) == 0
+    ptrs = []
+    for n in (1000, 256, 70000, 1):
+        p = C.c_void_p()
+        assert L.smmo_arena_alloc(h, n, C.byref(p)) == 0
+        assert p.value % 256 == 0 and base <= p.value < base + (1 << 20)
+        ptrs.append((p.value, (n + 255) // 256 * 256))
+    spans = sorted(ptrs)
+    for (a, na), (b, nb) in zip(spans, spans[1:]):
+        assert a + na <= b                                  # no overlap
+    big = C.c_void_p()
+    assert L.smmo_arena_alloc(h, 1 << 20, C.byref(big)) == -3   # does not fit
+    for p, _ in ptrs:
+        assert L.smmo_arena_free(h, C.c_void_p(p)) == 0
+    free, largest = C.c_uint64(), C.c_uint64()
+    L.smmo_arena_stats(h, C.byref(free), C.byref(largest))
+    assert free.value == largest.value == 1 << 20              # fully merged again
+    assert L.smmo_arena_free(h, C.c_void_p(base + 12345)) == -1
+    L.smmo_arena_destroy(h)
