@@ -122,7 +122,17 @@ __device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t 
         seed = splitmix64(seed);
         const uint32_t rot = rotate ? (uint32_t)seed & 63 : 0;
         const uint64_t mask = rotl64(lowest_k_bits(rotr64(freeb, rot), want), rot);
-        uint64_t before = at_or_acq(&h.alloc[bid], mask);
+        // The type read below must see the type written before the word this
+        // OR observed was re-initialized (Alg. 8's fence).  The writer
+        // publishes the word with a release store after the type; here the OR
+        // has returned before the type load is issued (it depends on `got`
+        // through the branch, and the compiler may not move it up), and the
+        // type load is a device-scope load, so it reads at the device
+        // coherence point, where the type already is.  An acquire on the OR
+        // would also invalidate this CU's caches on every reservation, which
+        // more than doubled the allocating do-alls' time on MI355X.
+        uint64_t before = at_or(&h.alloc[bid], mask);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         count(h, SMMO_CNT_RESERVE_ATOMIC);
         const uint64_t got = mask & ~before;
         if (!got) { count(h, SMMO_CNT_RESERVE_FAIL); continue; }

@@ -690,9 +690,9 @@ int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
     smmo_batch* B = new smmo_batch();
     B->arena = arena;
     B->max_inst = max_inst;
-    // every workgroup must be resident at once for the instance barriers;
-    // stay at half the reported occupancy for margin
-    B->grid = (uint32_t)cus * (uint32_t)std::max(1, std::min(per_cu / 2, 4));
+    // every workgroup must be resident at once for the instance barriers: the
+    // grid is the occupancy the runtime reports for this kernel (capped)
+    B->grid = (uint32_t)cus * (uint32_t)std::max(1, std::min(per_cu, 8));
     const uint64_t bytes = align_up(sizeof(BatchDesc) * max_inst, 256) + align_up(sizeof(BatchProg) * max_inst, 256) +
                            align_up(sizeof(BatchSched) * max_inst, 256) + align_up(4ull * B->grid, 256) +
                            align_up(4ull * max_inst, 256);

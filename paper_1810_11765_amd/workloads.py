@@ -106,12 +106,13 @@ class LifeGrid:
 
 
 def wator_blocks(kind0: np.ndarray) -> int:
-    """Heap blocks for a predator-prey instance: 4.5x the blocks its initial
-    fish (64 per block) and sharks (42 per block) fill, plus 16.  The oracle
-    shows the population peaking at up to ~3.15x its initial size under these
-    rules, so the 2x of a plain reading would run out of blocks."""
-    nf, ns = int((kind0 == 1).sum()), int((kind0 == 2).sum())
-    return int(4.5 * (-(-nf // 64) + -(-ns // 42))) + 16
+    """Heap blocks for a predator-prey instance: room for every cell holding
+    an object of the largest class (capacity 42) plus 50% for fragmentation,
+    plus 64.  The oracle shows the population peaking at up to ~3.15x its
+    initial size under these rules, so "2x the initial object count" runs out
+    of blocks; this bound holds at any population."""
+    n = int(kind0.size)
+    return (3 * n + 83) // 84 + 64
 
 
 class WaTor:
