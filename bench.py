@@ -36,8 +36,11 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-sub", action="store_true", help="skip the alloc / sweep sub-measurements")
+    p.add_argument("--no-sub", action="store_true", help="skip the alloc / sweep / batch sub-measurements")
+    p.add_argument("--no-batch", action="store_true", help="skip the plain-vs-batched sub-measurement")
     p.add_argument("--sweep-blocks", type=int, default=1 << 21)
+    p.add_argument("--calib-copy", action="store_true",
+                   help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
     return p.parse_args()
 
 
@@ -70,17 +73,34 @@ def life_bench(torch, workloads, steps, warmup):
             g0.step()
         torch.cuda.synchronize()
         del g0
+    # eager: K whole steps launched one do-all at a time
+    ge = workloads.LifeGrid(seed=42)
+    ge.populate()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ge.step()
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / steps
+    # timed region: the same K steps captured once in a HIP graph (capture runs
+    # nothing), then replayed from the freshly populated state
     g = workloads.LifeGrid(seed=42)
     g.populate()
     torch.cuda.synchronize()
-    # timed region: K whole steps, nothing else queued
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        g.step()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(steps):
+                g.step(stream=side)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / steps
+    t0 = time.perf_counter()
+    graph.replay()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
     status = g.heap.status()
+    same = all((a == b).all() for a, b in zip(g.state(), ge.state()))
+    del graph
     # per-kernel durations: the same K steps again from a fresh grid, each
     # do-all bracketed by events on the stream it is launched on
     g2 = workloads.LifeGrid(seed=42)
@@ -92,7 +112,7 @@ def life_bench(torch, workloads, steps, warmup):
         tm.run("commit", lambda: g2.heap.parallel_do(g2.CELL, S.M_LIFE_COMMIT, g2.args))
     torch.cuda.synchronize()
     per = {k: sum(tm.ms(k)) / steps for k in ("plan", "agent", "commit")}
-    return ms_step, per, status, g
+    return ms_step, per, status, {"eager_steps_s": round(1e3 / ms_eager, 2), "graph_equals_eager": bool(same)}
 
 
 def roofline_for(per_ms):
@@ -108,12 +128,38 @@ def roofline_for(per_ms):
     name = max(per_ms, key=per_ms.get)
     cells = 512 * 512
     bytes_per = {"plan": 18.0 * cells, "commit": 10.0 * cells, "agent": 21.0 * cells * 0.3}
+    kernel = {"plan": "k_doall<MLifePlan>", "agent": "k_doall<MLifeAgent>", "commit": "k_doall<MLifeCommit>"}[name]
     ms = per_ms[name]
     achieved = bytes_per[name] / (ms * 1e-3) / 1e9
     return name, {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                  "kernel": f"k_doall<{ {'plan': 'MLifePlan', 'agent': 'MLifeAgent', 'commit': 'MLifeCommit'}[name]}>",
-                  "ms_per_launch": round(ms, 5), "bytes_per_launch": int(bytes_per[name])}
+                  "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(kernel),
+                  "kernel": kernel, "ms_per_launch": round(ms, 5), "bytes_per_launch": int(bytes_per[name])}
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; counter figures taken on other sources are stale."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1810_11765_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs recorded in profiles/traffic.json (each counter scaled by
+    its reading on a plain copy of known size), or None when that record was
+    taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
 
 
 def alloc_sub(torch, workloads):
@@ -160,7 +206,25 @@ def sweep_sub(torch, nblocks):
     torch.cuda.synchronize()
     ms = sorted(tm.ms("sweep"))[len(tm.ms("sweep")) // 2]
     gbs = 12.0 * n / (ms * 1e-3) / 1e9
+    del h
+    # reference: the vendor elementwise kernel on the same access mix (two
+    # 512 MiB float reads, one 512 MiB write), i.e. what plain arrays reach
+    a = torch.empty(1 << 27, dtype=torch.float32, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.ones_like(a)
+    for _ in range(3):
+        torch.add(b, c, alpha=0.5, out=a)
+    ref = Timer(torch)
+    for _ in range(20):
+        ref.run("ref", lambda: torch.add(b, c, alpha=0.5, out=a))
+    torch.cuda.synchronize()
+    ref_ms = sorted(ref.ms("ref"))[10]
+    ref_gbs = 3.0 * a.numel() * 4 / (ref_ms * 1e-3) / 1e9
+    del a, b, c
     return {"objects": n, "bytes_per_sweep": 12 * n, "ms_median": round(ms, 4), "gbs": round(gbs, 1),
+            "kernel": "k_doall_axpy<2>", "traffic": measured_traffic("k_doall_axpy<2>@2^21"),
+            "plain_array_reference_gbs": round(ref_gbs, 1),
+            "fraction_of_plain_array_reference": round(gbs / ref_gbs, 3),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "status": h.status()}
 
 
@@ -225,7 +289,7 @@ def main():
         sys.exit(1)
     from paper_1810_11765_amd import smmo, workloads
     smmo.lib()                                   # fail loudly if the library is missing
-    ms_step, per, status, g = life_bench(torch, workloads, args.steps, args.warmup)
+    ms_step, per, status, life_extra = life_bench(torch, workloads, args.steps, args.warmup)
     kname, roof = roofline_for(per)
     out = {
         "metric": METRIC,
@@ -241,15 +305,24 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "life-like grid 512x512 torus, density 0.3, 200 steps, 16384-block heap, "
-                               "Cell{i32,i32,i8} + Agent{i32,i32}", "seed": 42, "mode": "plain"},
+                               "Cell{i32,i32,i8} + Agent{i32,i32}", "seed": 42, "mode": "hip-graph replay of the 200 steps"},
         "kernel_ms_per_step": {k: round(v, 5) for k, v in per.items()},
+        "life_eager": life_extra,
         "roofline": roof,
         "device_status": status,
     }
     if not args.no_sub:
         out["alloc_microbench"] = alloc_sub(torch, workloads)
         out["sweep"] = sweep_sub(torch, args.sweep_blocks)
-        out["predator_prey_plain_vs_batched"] = batch_sub(torch)
+        if not args.no_batch:
+            out["predator_prey_plain_vs_batched"] = batch_sub(torch)
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
