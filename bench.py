@@ -206,6 +206,7 @@ def sweep_sub(torch, nblocks):
     torch.cuda.synchronize()
     ms = sorted(tm.ms("sweep"))[len(tm.ms("sweep")) // 2]
     gbs = 12.0 * n / (ms * 1e-3) / 1e9
+    status = h.status()
     del h
     # reference: the vendor elementwise kernel on the same access mix (two
     # 512 MiB float reads, one 512 MiB write), i.e. what plain arrays reach
@@ -225,7 +226,7 @@ def sweep_sub(torch, nblocks):
             "kernel": "k_doall_axpy<2>", "traffic": measured_traffic("k_doall_axpy<2>@2^21"),
             "plain_array_reference_gbs": round(ref_gbs, 1),
             "fraction_of_plain_array_reference": round(gbs / ref_gbs, 3),
-            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "status": h.status()}
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "status": status}
 
 
 def batch_sub(torch, steps=200, count=256):

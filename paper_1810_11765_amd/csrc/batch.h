@@ -60,12 +60,22 @@ __device__ inline void batch_phase(const DevHeap& h, uint32_t cls, const smmo_wa
     const typename M::Prep prep = M::prepare(h, cls, a);
     for (uint64_t u = wave_rank; u < nunits; u += nwaves) {
         const uint64_t w = u >> 2;
-        uint64_t word = at_load(l0 + w) & (0xFFFFull << ((u & 3) * 16));
+        const uint32_t first = (uint32_t)(u & 3) * 16;
+        const uint64_t my_blk = (w << 6) + first + lane;
+        const bool mine = lane < 16 && my_blk < h.M;
+        uint64_t my_word = 0, word;
+        if (!M::kSnapshot) {       // no block of the class appears during a plan phase
+            if (mine) my_word = at_load(&h.alloc[my_blk]);
+            word = at_load(l0 + w) & (0xFFFFull << first);
+        } else {
+            word = at_load(l0 + w) & (0xFFFFull << first);
+            if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
+        }
         while (word) {
             const uint32_t b = ctz64(word);
             word &= word - 1;
             const uint64_t bid = (w << 6) | b;
-            const uint64_t live = (M::kSnapshot ? at_load(&h.iter[bid]) : at_load(&h.alloc[bid])) & valid;
+            const uint64_t live = (uint64_t)__shfl((unsigned long long)my_word, (int)(b - first), 64) & valid;
             Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
                   wave_seed(((uint64_t)a.step << 20) ^ wave_rank, bid)};
             M::run(o, prep, a);

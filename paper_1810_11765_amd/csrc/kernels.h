@@ -104,13 +104,28 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls
     const typename M::Prep prep = M::prepare(h, cls, a);
     for (uint64_t u = wave; u < nunits; u += nwaves) {
         const uint64_t w = u >> s_log2;
-        const uint32_t sub = (uint32_t)(u & ((1u << s_log2) - 1));
-        uint64_t word = at_load(l0 + w) & (span_mask << (sub * span));
+        const uint32_t first = (uint32_t)(u & ((1u << s_log2) - 1)) * span;   // first block bit of the unit
+        const uint64_t my_blk = (w << 6) + first + lane;                       // lane l: block first + l
+        const bool mine = lane < span && my_blk < h.M;
+        uint64_t my_word = 0, word;
+        if (!M::kSnapshot) {
+            // The class gains no block during this do-all and a block leaves
+            // only through its own wave, so the words can be fetched together
+            // with the bitmap word; words of blocks whose bit is clear are
+            // never used.
+            if (mine) my_word = h.alloc[my_blk];
+            word = l0[w] & (span_mask << first);
+        } else {
+            // Blocks may be (re)initialized meanwhile: read the bitmap word
+            // first, then the iteration words of its set bits.
+            word = at_load(l0 + w) & (span_mask << first);
+            if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
+        }
         while (word) {
             const uint32_t b = ctz64(word);
             word &= word - 1;
             const uint64_t bid = (w << 6) | b;
-            const uint64_t live = (M::kSnapshot ? at_load(&h.iter[bid]) : at_load(&h.alloc[bid])) & valid;
+            const uint64_t live = (uint64_t)__shfl((unsigned long long)my_word, (int)(b - first), 64) & valid;
             Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
                   wave_seed(wave, bid)};
             M::run(o, prep, a);
