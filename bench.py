@@ -41,6 +41,9 @@ def parse():
     p.add_argument("--sweep-blocks", type=int, default=1 << 21)
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
+    p.add_argument("--suite", choices=["ablation", "linux-scalability", "heap-size"],
+                   help="run one of the allocator studies instead of the headline and print its JSON line")
+    p.add_argument("--suite-steps", type=int, default=None, help="predator-prey steps of a suite run")
     return p.parse_args()
 
 
@@ -262,6 +265,167 @@ def batch_sub(torch, steps=200, count=256):
             "identical_results": bool(same), "status": int(status)}
 
 
+def _progress(*a):
+    print("[suite]", *a, file=sys.stderr, flush=True)
+
+
+def _wator_same(w, oracle_state):
+    import numpy as np
+    kind, age, energy = w.state()
+    ok, oa, oe = oracle_state
+    return bool(np.array_equal(kind, ok) and np.array_equal(age[kind > 0], oa[ok > 0]) and
+                np.array_equal(energy[kind == 2], oe[ok == 2]))
+
+
+ABLATION_VARIANTS = [("default", 0, 5), ("noshift", 1, 5), ("nocoal", 2, 5), ("nocoal-noshift", 3, 5),
+                     ("r1", 0, 1), ("r2", 0, 2), ("r3", 0, 3), ("r5", 0, 5), ("r8", 0, 8)]
+
+
+def ablation_suite(torch, workloads, steps):
+    """Predator-prey 1024 x 1024 (seed 42, 32,768-block heap) under each
+    allocator variant of Sec. 6.3: rotation off (noshift), request
+    coalescing off (nocoal), both, and r = 1..8 active-block lookups.  Per
+    variant: step time (events around each step), fragmentation F every 10
+    steps (occupancy query, outside the timed spans) and whether the final
+    state equals the oracle's."""
+    from oracle import core
+    from paper_1810_11765_amd import smmo as S
+    seed, side = 42, 1024
+    kind0 = None
+    out = {}
+    for name, flags, lookups in ABLATION_VARIANTS:
+        _progress("ablation", name)
+        w = workloads.WaTor(seed=seed, width=side, height=side, kind0=kind0)
+        kind0 = w.kind0
+        w.heap.set_tuning(flags, lookups, 0)
+        w.populate()
+        tm = Timer(torch)
+        F = []
+        for st in range(1, steps + 1):
+            tm.run("step", w.step)
+            if st % 10 == 0:
+                F.append(round(w.heap.occupancy()["F"], 5))
+        torch.cuda.synchronize()
+        ms = tm.ms("step")
+        out[name] = {"flags": flags, "lookups": lookups, "ms_per_step": round(sum(ms) / len(ms), 5),
+                     "ms_total": round(sum(ms), 3), "F_every_10_steps": F,
+                     "F_mean_last_100": round(sum(F[-10:]) / len(F[-10:]), 5), "status": w.heap.status(),
+                     "_w": w}
+    _progress("ablation oracle")
+    ref = core.c3_run(kind0, side, side, seed, steps)
+    for name in out:
+        w = out[name].pop("_w")
+        out[name]["identical_to_oracle"] = _wator_same(w, ref)
+        w.heap.close()
+    return {"workload": f"predator-prey {side}x{side} torus, seed {seed}, 32768-block heap, {steps} steps",
+            "variants": out}
+
+
+def linux_scalability_suite(torch, workloads):
+    """Raw allocation (Sec. 6.4): 16,384 threads each allocate n 64-byte
+    objects without touching them (one kernel), then destroy them by handle
+    (a second kernel); the heap's whole device footprint is 1 GiB.  n from 1
+    to 1024; the paper's measure is (alloc + destroy time) / n."""
+    from paper_1810_11765_amd import smmo as S
+    ls = workloads.LinuxScalability()
+    cap = ls.num_blocks * 64
+    rows = []
+    n = 1
+    while n <= 1024:
+        _progress("linux-scalability n", n)
+        reps = 3 if n < 1024 else 1
+        a_ms, f_ms = [], []
+        live = 0
+        status = 0
+        for _ in range(reps):
+            ls.heap.reset()
+            tm = Timer(torch)
+            tm.run("alloc", lambda: ls.alloc(n))
+            torch.cuda.synchronize()
+            live = ls.heap.live_count(0)
+            status = ls.heap.status()
+            tm.run("free", lambda: ls.free(n))
+            torch.cuda.synchronize()
+            left = ls.heap.live_count(0)
+            a_ms += tm.ms("alloc")
+            f_ms += tm.ms("free")
+            ls.heap.clear_status()
+        a, f = sorted(a_ms)[len(a_ms) // 2], sorted(f_ms)[len(f_ms) // 2]
+        rows.append({"n": n, "alloc_ms": round(a, 4), "destroy_ms": round(f, 4),
+                     "total_ms_over_n": round((a + f) / n, 5),
+                     "ns_per_alloc": round(a * 1e6 / (16384 * n), 4),
+                     "ns_per_destroy": round(f * 1e6 / (16384 * n), 4),
+                     "live_after_alloc": live, "requested": 16384 * n, "left_after_destroy": left,
+                     "oom": bool(status & S.STATUS_OOM)})
+        n *= 2
+    top = rows[-1]
+    return {"workload": "16384 threads x n allocations of a 64-byte class, heap footprint 1 GiB",
+            "num_blocks": ls.num_blocks, "slots": cap, "heap_bytes": S.heap_bytes(ls.CLASSES, ls.num_blocks),
+            "utilization_at_1024": round(top["live_after_alloc"] * 64 / (1 << 30), 5),
+            "rows": rows}
+
+
+def blocks_for_bytes(classes, total: int) -> int:
+    from paper_1810_11765_amd import smmo as S
+    lo, hi = 1, total // 64 + 1
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if S.heap_bytes(classes, mid) <= total:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+def heap_size_suite(torch, workloads, steps):
+    """Predator-prey 1024 x 1024 (seed 42) in heaps of 1 to 64 GiB (Sec. 6.5):
+    step time with the level-1 skip (default) and with every level-0 word
+    scanned (flat), and whether the final state equals the oracle's."""
+    from oracle import core
+    from paper_1810_11765_amd import smmo as S
+    seed, side = 42, 1024
+    kind0 = None
+    rows = []
+    for gib in (1, 2, 4, 8, 16, 32, 64):
+        nb = blocks_for_bytes(workloads.WaTor.CLASSES, gib << 30)
+        row = {"heap_gib": gib, "num_blocks": nb}
+        for mode in ("hierarchical", "flat"):
+            _progress("heap-size", gib, mode)
+            w = workloads.WaTor(seed=seed, width=side, height=side, num_blocks=nb, kind0=kind0)
+            kind0 = w.kind0
+            if mode == "flat":
+                w.heap.set_tuning(S.TUNE_FLAT_ENUM, 5, 0)
+            w.populate()
+            tm = Timer(torch)
+            for _ in range(steps):
+                tm.run("step", w.step)
+            torch.cuda.synchronize()
+            ms = tm.ms("step")
+            row[mode] = {"ms_per_step": round(sum(ms) / len(ms), 5), "status": w.heap.status(), "_w": w}
+            if mode == "hierarchical":
+                row[mode]["F_end"] = round(w.heap.occupancy()["F"], 5)
+            if gib == 1 and mode == "hierarchical":
+                _progress("heap-size oracle")
+                ref = core.c3_run(kind0, side, side, seed, steps)
+            row[mode]["identical_to_oracle"] = _wator_same(w, ref)
+            row[mode].pop("_w")
+            w.heap.close()
+            del w
+            torch.cuda.empty_cache()
+        rows.append(row)
+    return {"workload": f"predator-prey {side}x{side} torus, seed {seed}, {steps} steps", "rows": rows}
+
+
+def run_suite(args, torch, workloads):
+    if args.suite == "ablation":
+        res = ablation_suite(torch, workloads, args.suite_steps or 500)
+    elif args.suite == "linux-scalability":
+        res = linux_scalability_suite(torch, workloads)
+    else:
+        res = heap_size_suite(torch, workloads, args.suite_steps or 100)
+    print(json.dumps({"suite": args.suite, **res}), flush=True)
+
+
 def cpu_baseline():
     """The CPU oracle's Life run (single thread) on whole 200-step runs of the
     same 512 x 512 workload, repeated until about 10 s of CPU time."""
@@ -290,6 +454,9 @@ def main():
         sys.exit(1)
     from paper_1810_11765_amd import smmo, workloads
     smmo.lib()                                   # fail loudly if the library is missing
+    if args.suite:
+        run_suite(args, torch, workloads)
+        return
     ms_step, per, status, life_extra = life_bench(torch, workloads, args.steps, args.warmup)
     kname, roof = roofline_for(per)
     out = {

@@ -131,13 +131,16 @@ enum smmo_counter {
 #define SMMO_TUNE_FORCE_FAIL 8u     /* try_find_set fails force_fail_ppm / 1e6 of the time */
 #define SMMO_TUNE_SLOW_PICK 16u     /* pause ~20 us between picking an active block and
                                        reserving in it (widens the race window of App. A.3) */
+#define SMMO_TUNE_FLAT_ENUM 32u     /* do-all, snapshot and live count scan every level-0
+                                       word even in big heaps (no level-1 skip) */
 
 /* -------------------------------------------------- heap management ---- */
 
 /* Bytes of device memory a heap of `num_blocks` blocks for these classes
  * needs (metadata + scratch + data).  Classes: 1..SMMO_MAX_CLASSES, each with
  * 1..SMMO_MAX_FIELDS fields; no class may be more than 64x the smallest
- * (Sec. 3.2).  num_blocks: 1..2^36.  Errors: SMMO_EINVAL. */
+ * (Sec. 3.2).  num_blocks: 1..2^32 (block ids are kept in 32 bits by the
+ * enumeration lists).  Errors: SMMO_EINVAL. */
 int smmo_heap_bytes(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks,
                     uint64_t* bytes_out);
 
@@ -175,6 +178,8 @@ int smmo_set_tuning(smmo_heap* heap, uint32_t flags, uint32_t lookups, uint32_t 
  * parallel_new passes 0..n-1). */
 #define SMMO_CTOR_ZERO 0u           /* all fields zero; args unused */
 #define SMMO_CTOR_ARRAYS 1u         /* fields from device arrays, see below */
+#define SMMO_CTOR_NONE 2u           /* object memory untouched (the raw allocation
+                                       benchmark of Sec. 6.4); see smmo_ctor_none */
 
 /* Argument blob of SMMO_CTOR_ARRAYS: field f of object i = src[f][i] (src[f]
  * NULL: zero).  If ref_out is non-NULL the new handle is stored at
@@ -184,6 +189,13 @@ typedef struct smmo_ctor_arrays {
     uint64_t* ref_out;
     const int32_t* ref_index;
 } smmo_ctor_arrays;
+
+/* Argument blob of SMMO_CTOR_NONE (may be omitted: args NULL, 0 bytes): if
+ * ref_out is non-NULL the new handle of object i is stored at ref_out[i]
+ * (device pointer); the object's fields are never written. */
+typedef struct smmo_ctor_none {
+    uint64_t* ref_out;
+} smmo_ctor_none;
 
 /* ---------------------------------------------------------- methods ---- */
 /* method_id values for smmo_parallel_do.  A method runs once on every object
@@ -323,6 +335,17 @@ int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_i
 int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32_t per_thread,
                         uint32_t ctor_id, const void* args, uint64_t args_bytes, void* stream);
 
+/* Device-side destruction from a kernel of `nthreads` threads, thread t
+ * calling destroy(refs[t*per_thread + k]) for k = 0..per_thread-1 in sequence
+ * (Sec. 2.1 "destroy"; Alg. 2), the mirror of smmo_parallel_alloc.  refs is a
+ * device array of nthreads*per_thread handles; 0 (null) entries are skipped.
+ * Destructions of one wave that hit the same block are combined into one
+ * atomic update.  Every non-null handle must name a live object and appear at
+ * most once; this is not checked beyond flagging SMMO_STATUS_CORRUPT when a
+ * slot is freed twice. */
+int smmo_parallel_destroy(smmo_heap* heap, const uint64_t* refs, uint64_t nthreads, uint32_t per_thread,
+                          void* stream);
+
 /* parallel_do<T, method> (Sec. 2.1, Sec. 3.7): run `method_id` on every live
  * object of class `cls`.  args: the method's blob (<= SMMO_ARGS_MAX bytes). */
 int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
@@ -330,6 +353,12 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
 
 /* Live objects of class `cls`.  Synchronizes the stream. */
 int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream);
+
+/* Slot occupancy per class (Sec. 6.3, the fragmentation measure): for each
+ * class c < ncls, used[c] = live objects, slots[c] = N_c times blocks[c],
+ * blocks[c] = blocks allocated to c.  Fragmentation F = 1 - sum(used) /
+ * sum(slots).  Host arrays of ncls entries.  Synchronizes the stream. */
+int smmo_occupancy(smmo_heap* heap, uint64_t* used, uint64_t* slots, uint64_t* blocks, void* stream);
 
 /* Copy every live object of `cls` to host SOA arrays (host_field_bufs[f] has
  * room for `cap` values of field f), in block order then slot order; *n_out

@@ -57,14 +57,57 @@ __global__ void k_fill_u64(unsigned long long* p, uint64_t n, uint64_t v) {
     if (i < n) p[i] = v;
 }
 
+// ------------------------------------------- hierarchical enumeration ----
+// Indices of the non-empty level-0 words of bitmap `bmid`, found through
+// level 1 (Alg. 5 / Sec. 4.1.5: containers whose nested bit is clear are never
+// read), appended in any order to words[]; *count must be 0 on entry.  One
+// thread per level-1 word.  Used for big heaps so that a do-all costs the
+// occupied part of the heap, not its size (Sec. 6.5).
+__global__ void k_enum_words(DevHeap h, uint32_t bmid, uint32_t* words, unsigned long long* count) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t w1 = 0;
+    if (j < h.level_words[1]) w1 = *bm_word(h, bmid, 1, j);
+    const uint32_t n = popc64(w1);
+    // one counter update per wave: exclusive prefix of n inside the wave
+    uint32_t incl = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o, 64);
+        if (lane_id() >= (uint32_t)o) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    unsigned long long base = 0;
+    if (lane_id() == 63 && total) base = atomicAdd(count, (unsigned long long)total);
+    base = __shfl(base, 63, 64);
+    uint64_t pos = base + incl - n;
+    while (w1) {
+        words[pos++] = (uint32_t)((j << 6) | ctz64(w1));
+        w1 &= w1 - 1;
+    }
+}
+
 // --------------------------------------------------- iteration snapshot ----
 // iter <- alloc (without padding) for every allocated block of `cls`, before
 // a do-all whose method may create objects of its own class (Sec. 3.1).
-__global__ void k_snapshot(DevHeap h, uint32_t cls) {
-    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= h.M) return;
-    uint64_t w = *bm_word(h, bm_allocated(cls), 0, b >> 6);
-    if ((w >> (b & 63)) & 1) h.iter[b] = h.alloc[b] & ~h.cls_pad[cls];
+// Direct form: one thread per block.  List form (big heaps): one wave per
+// non-empty level-0 word of allocated[cls], lane = block of that word.
+__global__ void k_snapshot(DevHeap h, uint32_t cls, const uint32_t* words, const unsigned long long* nwords) {
+    const uint64_t valid = ~h.cls_pad[cls];
+    if (!words) {
+        uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (b >= h.M) return;
+        uint64_t w = *bm_word(h, bm_allocated(cls), 0, b >> 6);
+        if ((w >> (b & 63)) & 1) h.iter[b] = h.alloc[b] & valid;
+        return;
+    }
+    const uint64_t n = *nwords;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t e = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < n; e += nwaves) {
+        const uint64_t wi = words[e];
+        const uint64_t w = *bm_word(h, bm_allocated(cls), 0, wi);
+        const uint64_t b = (wi << 6) | lane_id();
+        if ((w >> lane_id()) & 1) h.iter[b] = h.alloc[b] & valid;
+    }
 }
 
 // ----------------------------------------------------------- do-all ----
@@ -91,9 +134,12 @@ struct Obj {
 // iteration word written by k_snapshot (blocks initialized meanwhile have it
 // zeroed), otherwise no object of the class can appear during the do-all and
 // the allocation word itself is the snapshot.
+// With a word list (big heaps, from k_enum_words) unit u covers part of L0
+// word words[u >> s_log2] and the unit count is taken from the list length.
 template <class M>
 __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls, uint32_t s_log2,
-                                                          uint64_t nunits, typename M::Args a) {
+                                                          uint64_t nunits, const uint32_t* words,
+                                                          const unsigned long long* nwords, typename M::Args a) {
     const uint32_t lane = lane_id();
     const uint64_t wave = global_wave();
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -102,8 +148,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls
     const uint32_t span = 64u >> s_log2;
     const uint64_t span_mask = span == 64 ? kOnes : ((1ull << span) - 1);
     const typename M::Prep prep = M::prepare(h, cls, a);
+    if (words) nunits = (uint64_t)*nwords << s_log2;
     for (uint64_t u = wave; u < nunits; u += nwaves) {
-        const uint64_t w = u >> s_log2;
+        const uint64_t w = words ? (uint64_t)words[u >> s_log2] : u >> s_log2;
         const uint32_t first = (uint32_t)(u & ((1u << s_log2) - 1)) * span;   // first block bit of the unit
         const uint64_t my_blk = (w << 6) + first + lane;                       // lane l: block first + l
         const bool mine = lane < span && my_blk < h.M;
@@ -221,16 +268,65 @@ __global__ __launch_bounds__(kBlockThreads) void k_alloc(DevHeap h, uint32_t cls
     }
 }
 
+// ------------------------------------------------ device-side destroy ----
+// Thread t destroys refs[t*per + k] for k = 0..per-1 in sequence; lanes of a
+// wave whose handles share a block are combined (wave_destroy).
+__global__ __launch_bounds__(kBlockThreads) void k_destroy(DevHeap h, const uint64_t* refs, uint64_t nthreads,
+                                                            uint32_t per) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((global_wave() << 6) >= nthreads) return;         // wave-uniform
+    const bool act = tid < nthreads;
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint64_t r = act ? refs[tid * per + k] : 0;
+        wave_destroy(h, r, act);
+    }
+}
+
 // ------------------------------------------------------------ counting ----
-__global__ void k_live_count(DevHeap h, uint32_t cls, unsigned long long* out) {
-    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Live objects of `cls` -> *out (added).  Direct form: one thread per block;
+// list form: one wave per listed L0 word of allocated[cls].
+__global__ void k_live_count(DevHeap h, uint32_t cls, const uint32_t* words, const unsigned long long* nwords,
+                             unsigned long long* out) {
     uint32_t c = 0;
-    if (b < h.M) {
-        uint64_t w = *bm_word(h, bm_allocated(cls), 0, b >> 6);
-        if ((w >> (b & 63)) & 1) c = popc64(h.alloc[b] & ~h.cls_pad[cls]);
+    if (!words) {
+        uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (b < h.M) {
+            uint64_t w = *bm_word(h, bm_allocated(cls), 0, b >> 6);
+            if ((w >> (b & 63)) & 1) c = popc64(h.alloc[b] & ~h.cls_pad[cls]);
+        }
+    } else {
+        const uint64_t n = *nwords;
+        const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+        for (uint64_t e = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < n; e += nwaves) {
+            const uint64_t wi = words[e];
+            const uint64_t w = *bm_word(h, bm_allocated(cls), 0, wi);
+            if ((w >> lane_id()) & 1) c += popc64(h.alloc[(wi << 6) | lane_id()] & ~h.cls_pad[cls]);
+        }
     }
     c = wave_add(c);
     if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+// Per-class slot occupancy (the fragmentation measure): out[3c] += live
+// objects, out[3c+1] += N_c per block, out[3c+2] += blocks, over every block
+// whose free bit is clear (at rest such a block belongs to class type[b]).
+__global__ void k_occupancy(DevHeap h, unsigned long long* out) {
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t t = kNoType, used = 0;
+    if (b < h.M && !((*bm_word(h, bm_free(), 0, b >> 6) >> (b & 63)) & 1)) {
+        t = h.type[b];
+        if (t < h.ncls) used = popc64(h.alloc[b] & ~h.cls_pad[t]);
+    }
+    for (uint32_t c = 0; c < h.ncls; ++c) {
+        const uint32_t nb = (uint32_t)popc64(ballot(t == c));
+        if (!nb) continue;                                  // wave-uniform
+        const uint32_t u = wave_add(t == c ? used : 0u);
+        if (lane_id() == 0) {
+            atomicAdd(out + 3 * c, (unsigned long long)u);
+            atomicAdd(out + 3 * c + 1, (unsigned long long)nb * h.cls_cap[c]);
+            atomicAdd(out + 3 * c + 2, (unsigned long long)nb);
+        }
+    }
 }
 
 // -------------------------------------------------------- constructors ----
@@ -248,6 +344,14 @@ struct CtorZero {
                 default: *reinterpret_cast<uint64_t*>(p) = 0; break;
             }
         }
+    }
+};
+
+struct CtorNone {
+    using Args = smmo_ctor_none;
+    __device__ static void run(const DevHeap&, uint32_t, uint64_t, uint32_t, uint64_t i, uint64_t ref,
+                               const Args& a) {
+        if (a.ref_out) a.ref_out[i] = ref;
     }
 };
 

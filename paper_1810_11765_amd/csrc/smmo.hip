@@ -62,6 +62,7 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+constexpr uint64_t kScratchHead = 1024;                 // bytes of scratch counters
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 inline unsigned grid_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
@@ -70,7 +71,7 @@ inline unsigned grid_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1)
 // block has the size of the largest class layout.
 int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_raw_header* hdr) {
     if (!cls || ncls == 0 || ncls > SMMO_MAX_CLASSES) return fail(SMMO_EINVAL, "ncls must be 1..%d", SMMO_MAX_CLASSES);
-    if (M == 0 || M > (1ull << 36)) return fail(SMMO_EINVAL, "num_blocks must be 1..2^36");
+    if (M == 0 || M > (1ull << 32)) return fail(SMMO_EINVAL, "num_blocks must be 1..2^32");
     std::memset(hdr, 0, sizeof *hdr);
     uint64_t size[SMMO_MAX_CLASSES];
     uint64_t smin = ~0ull;
@@ -129,7 +130,8 @@ int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_r
     hdr->off_iter = p;         p = align_up(p + 8 * M, 256);
     hdr->off_bitmaps = p;      p = align_up(p + 8 * hdr->bitmap_words * (1 + 2 * (uint64_t)ncls), 256);
     hdr->off_scratch = p;
-    hdr->scratch_bytes = align_up(256 + 4 * M, 256);
+    // counters (1 KiB), block list R (4 B per block), L0 word list (4 B per L0 word)
+    hdr->scratch_bytes = align_up(kScratchHead + 4 * M + 4 * hdr->level_words[0], 256);
     p += hdr->scratch_bytes;
     hdr->off_data = align_up(p, 4096);
     hdr->total_bytes = hdr->off_data + M * block;
@@ -187,7 +189,38 @@ int init_device(smmo_heap* H, hipStream_t s) {
 unsigned long long* scratch_counter(smmo_heap* H, int i) {
     return reinterpret_cast<unsigned long long*>(H->dev.scratch) + i;
 }
-uint32_t* scratch_R(smmo_heap* H) { return reinterpret_cast<uint32_t*>(H->dev.scratch + 256); }
+// scratch counters: 0 parallel_new's found, 1 live count, 2 n-body's found,
+// 3 word-list length, 8.. occupancy (3 per class)
+uint32_t* scratch_R(smmo_heap* H) { return reinterpret_cast<uint32_t*>(H->dev.scratch + kScratchHead); }
+uint32_t* scratch_words(smmo_heap* H) {
+    return reinterpret_cast<uint32_t*>(H->dev.scratch + kScratchHead + 4 * H->hdr.num_blocks);
+}
+
+#ifndef SMMO_LIST_MIN_WORDS
+#define SMMO_LIST_MIN_WORDS 4096   // L0 words from which enumeration goes through level 1
+#endif
+
+// Big heaps: list the non-empty L0 words of allocated[cls] via level 1, so
+// that the passes after it cost the class's blocks, not the heap's size.
+// Returns false (nothing launched) when the heap is scanned flat.
+bool build_word_list(smmo_heap* H, uint32_t cls, hipStream_t s, int* rc) {
+    *rc = SMMO_OK;
+    if (H->hdr.nlevels < 2 || H->hdr.level_words[0] < SMMO_LIST_MIN_WORDS || (H->dev.tune & SMMO_TUNE_FLAT_ENUM))
+        return false;
+    unsigned long long* cnt = scratch_counter(H, 3);
+    k_fill_u64<<<1, 64, 0, s>>>(cnt, 1, 0);
+    if (hipGetLastError() != hipSuccess) { *rc = fail(SMMO_EHIP, "k_fill_u64 launch"); return false; }
+    k_enum_words<<<grid_for(H->hdr.level_words[1], 256), 256, 0, s>>>(H->dev, bm_allocated(cls), scratch_words(H), cnt);
+    if (hipGetLastError() != hipSuccess) { *rc = fail(SMMO_EHIP, "k_enum_words launch"); return false; }
+    return true;
+}
+
+// grid for the list-form passes: at most one wave per L0 word, at most 32
+// waves per CU, grid-stride beyond
+unsigned list_grid(const smmo_heap* H) {
+    const uint64_t waves = std::min<uint64_t>(H->hdr.level_words[0], 256ull * 32);
+    return (unsigned)((waves + 3) / 4);
+}
 
 int check_heap_cls(const smmo_heap* H, uint32_t cls) {
     if (!H) return fail(SMMO_EINVAL, "null heap");
@@ -224,15 +257,27 @@ int launch_doall(smmo_heap* H, uint32_t cls, const void* args, uint64_t bytes, h
     typename M::Args a;
     int rc = unpack_args(a, args, bytes, "parallel_do");
     if (rc) return rc;
+    const bool list = build_word_list(H, cls, s, &rc);
+    if (rc) return rc;
+    const uint32_t* words = list ? scratch_words(H) : nullptr;
+    const unsigned long long* nwords = list ? scratch_counter(H, 3) : nullptr;
     if (M::kSnapshot) {
-        k_snapshot<<<grid_for(H->hdr.num_blocks, 256), 256, 0, s>>>(H->dev, cls);
+        if (list) k_snapshot<<<list_grid(H), 256, 0, s>>>(H->dev, cls, words, nwords);
+        else k_snapshot<<<grid_for(H->hdr.num_blocks, 256), 256, 0, s>>>(H->dev, cls, nullptr, nullptr);
         LAUNCH_CHECK("k_snapshot");
     }
     uint32_t s_log2;
     uint64_t nunits;
     unsigned grid;
     doall_geometry(H, s_log2, nunits, grid);
-    k_doall<M><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, a);
+    if (list) {
+        // the list length is known on the device only: units of 16 blocks
+        // keep a sparse class spread over many waves
+        s_log2 = 2;
+        nunits = 0;
+        grid = (unsigned)((std::min<uint64_t>(H->hdr.level_words[0] << 2, 256ull * 32) + 3) / 4);
+    }
+    k_doall<M><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, words, nwords, a);
     LAUNCH_CHECK("k_doall");
     return SMMO_OK;
 }
@@ -398,6 +443,7 @@ int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_i
     switch (ctor_id) {
         case SMMO_CTOR_ZERO: return launch_new<CtorZero>(heap, cls, n, args, args_bytes, S(stream));
         case SMMO_CTOR_ARRAYS: return launch_new<CtorArrays>(heap, cls, n, args, args_bytes, S(stream));
+        case SMMO_CTOR_NONE: return launch_new<CtorNone>(heap, cls, n, args, args_bytes, S(stream));
         default: return fail(SMMO_EINVAL, "unknown ctor_id %u", ctor_id);
     }
 }
@@ -412,8 +458,22 @@ int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32
             return launch_alloc<CtorZero>(heap, cls, nthreads, per_thread, args, args_bytes, S(stream));
         case SMMO_CTOR_ARRAYS:
             return launch_alloc<CtorArrays>(heap, cls, nthreads, per_thread, args, args_bytes, S(stream));
+        case SMMO_CTOR_NONE:
+            return launch_alloc<CtorNone>(heap, cls, nthreads, per_thread, args, args_bytes, S(stream));
         default: return fail(SMMO_EINVAL, "unknown ctor_id %u", ctor_id);
     }
+}
+
+int smmo_parallel_destroy(smmo_heap* heap, const uint64_t* refs, uint64_t nthreads, uint32_t per_thread,
+                          void* stream) {
+    if (!heap) return fail(SMMO_EINVAL, "null heap");
+    if (nthreads == 0 || per_thread == 0) return SMMO_OK;
+    if (!refs) return fail(SMMO_EINVAL, "null refs");
+    if (nthreads > (1ull << 40)) return fail(SMMO_EINVAL, "nthreads too large");
+    k_destroy<<<grid_for(nthreads, kBlockThreads), kBlockThreads, 0, S(stream)>>>(heap->dev, refs, nthreads,
+                                                                                 per_thread);
+    LAUNCH_CHECK("k_destroy");
+    return SMMO_OK;
 }
 
 int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args, uint64_t args_bytes,
@@ -482,12 +542,38 @@ int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream) 
     unsigned long long* c = scratch_counter(heap, 1);
     k_fill_u64<<<1, 64, 0, s>>>(c, 1, 0);
     LAUNCH_CHECK("k_fill_u64");
-    k_live_count<<<grid_for(heap->hdr.num_blocks, 256), 256, 0, s>>>(heap->dev, cls, c);
+    const bool list = build_word_list(heap, cls, s, &rc);
+    if (rc) return rc;
+    if (list)
+        k_live_count<<<list_grid(heap), 256, 0, s>>>(heap->dev, cls, scratch_words(heap), scratch_counter(heap, 3), c);
+    else
+        k_live_count<<<grid_for(heap->hdr.num_blocks, 256), 256, 0, s>>>(heap->dev, cls, nullptr, nullptr, c);
     LAUNCH_CHECK("k_live_count");
     unsigned long long v = 0;
     HIP_TRY(hipMemcpyAsync(&v, c, sizeof v, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *out = v;
+    return SMMO_OK;
+}
+
+int smmo_occupancy(smmo_heap* heap, uint64_t* used, uint64_t* slots, uint64_t* blocks, void* stream) {
+    if (!heap) return fail(SMMO_EINVAL, "null heap");
+    if (!used || !slots || !blocks) return fail(SMMO_EINVAL, "null output array");
+    hipStream_t s = S(stream);
+    const uint32_t nc = (uint32_t)heap->hdr.ncls;
+    unsigned long long* c = scratch_counter(heap, 8);
+    k_fill_u64<<<1, 64, 0, s>>>(c, 3 * nc, 0);
+    LAUNCH_CHECK("k_fill_u64");
+    k_occupancy<<<grid_for(heap->hdr.num_blocks, 256), 256, 0, s>>>(heap->dev, c);
+    LAUNCH_CHECK("k_occupancy");
+    unsigned long long v[3 * SMMO_MAX_CLASSES];
+    HIP_TRY(hipMemcpyAsync(v, c, 3 * nc * sizeof v[0], hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (uint32_t t = 0; t < nc; ++t) {
+        used[t] = v[3 * t];
+        slots[t] = v[3 * t + 1];
+        blocks[t] = v[3 * t + 2];
+    }
     return SMMO_OK;
 }
 
@@ -500,32 +586,52 @@ static int dump_walk(smmo_heap* heap, uint32_t cls, void* const* bufs, uint64_t*
     if (!n_out) return fail(SMMO_EINVAL, "null n_out");
     const smmo_raw_header& h = heap->hdr;
     hipStream_t s = S(stream);
-    std::vector<uint8_t> raw(h.total_bytes);
-    HIP_TRY(hipMemcpyAsync(raw.data(), heap->base, h.total_bytes, hipMemcpyDeviceToHost, s));
+    // level 0 of allocated[cls], then only the runs of blocks it names (close
+    // runs merged), so the copy is the class's size, not the heap's
+    const uint64_t W0 = h.level_words[0];
+    std::vector<uint64_t> l0(W0);
+    HIP_TRY(hipMemcpyAsync(l0.data(), heap->base + h.off_bitmaps + 8 * ((1 + cls) * h.bitmap_words + h.level_off[0]),
+                           8 * W0, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const uint64_t* alloc = reinterpret_cast<const uint64_t*>(raw.data() + h.off_alloc);
-    const uint64_t* l0 = reinterpret_cast<const uint64_t*>(raw.data() + h.off_bitmaps) +
-                         (uint64_t)(1 + cls) * h.bitmap_words + h.level_off[0];
+    std::vector<std::pair<uint64_t, uint64_t>> runs;       // [first, last] block
+    for (uint64_t i = 0; i < W0; ++i)
+        for (uint64_t w = l0[i]; w; w &= w - 1) {
+            const uint64_t b = (i << 6) | (uint64_t)__builtin_ctzll(w);
+            if (!runs.empty() && b <= runs.back().second + 8) runs.back().second = b;
+            else runs.push_back({b, b});
+        }
     const uint64_t N = h.capacity[cls];
     const uint64_t valid = N >= 64 ? ~0ull : ((1ull << N) - 1);
+    std::vector<uint64_t> alloc;
+    std::vector<uint8_t> data;
     uint64_t n = 0;
-    for (uint64_t b = 0; b < h.num_blocks; ++b) {
-        if (!((l0[b >> 6] >> (b & 63)) & 1)) continue;
-        uint64_t w = alloc[b] & valid;
-        const uint8_t* blk = raw.data() + h.off_data + b * h.block_bytes;
-        while (w) {
-            uint32_t slot = (uint32_t)__builtin_ctzll(w);
-            w &= w - 1;
-            if (n < cap) {
-                if (refs) refs[n] = make_ref(cls, b, slot);
-                if (bufs)
-                    for (uint32_t f = 0; f < h.nfields[cls]; ++f) {
-                        if (!bufs[f]) continue;
-                        uint32_t fb = h.field_bytes[cls][f];
-                        std::memcpy(static_cast<uint8_t*>(bufs[f]) + n * fb, blk + h.field_off[cls][f] + slot * fb, fb);
-                    }
+    for (const auto& r : runs) {
+        const uint64_t nb = r.second - r.first + 1;
+        alloc.resize(nb);
+        data.resize(nb * h.block_bytes);
+        HIP_TRY(hipMemcpyAsync(alloc.data(), heap->base + h.off_alloc + 8 * r.first, 8 * nb, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(data.data(), heap->base + h.off_data + r.first * h.block_bytes, nb * h.block_bytes,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (uint64_t b = r.first; b <= r.second; ++b) {
+            if (!((l0[b >> 6] >> (b & 63)) & 1)) continue;
+            uint64_t w = alloc[b - r.first] & valid;
+            const uint8_t* blk = data.data() + (b - r.first) * h.block_bytes;
+            while (w) {
+                uint32_t slot = (uint32_t)__builtin_ctzll(w);
+                w &= w - 1;
+                if (n < cap) {
+                    if (refs) refs[n] = make_ref(cls, b, slot);
+                    if (bufs)
+                        for (uint32_t f = 0; f < h.nfields[cls]; ++f) {
+                            if (!bufs[f]) continue;
+                            uint32_t fb = h.field_bytes[cls][f];
+                            std::memcpy(static_cast<uint8_t*>(bufs[f]) + n * fb, blk + h.field_off[cls][f] + slot * fb,
+                                        fb);
+                        }
+                }
+                ++n;
             }
-            ++n;
         }
     }
     *n_out = n;

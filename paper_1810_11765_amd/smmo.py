@@ -20,6 +20,7 @@ MAX_FIELDS = 16
 # constructors
 CTOR_ZERO = 0
 CTOR_ARRAYS = 1
+CTOR_NONE = 2
 # methods
 M_AXPY = 0
 M_DESTROY_ALL = 1
@@ -42,6 +43,7 @@ TUNE_NO_ROTATE = 1
 TUNE_NO_COALESCE = 2
 TUNE_STATS = 4
 TUNE_FORCE_FAIL = 8
+TUNE_FLAT_ENUM = 32
 COUNTERS = ["alloc_obj", "free_obj", "block_init", "block_free", "inval_rollback", "type_rollback",
             "find_fail", "reserve_fail", "spin", "reserve_atomic"]
 
@@ -53,6 +55,10 @@ class ClassDesc(C.Structure):
 class Layout(C.Structure):
     _fields_ = [("capacity", C.c_uint32), ("nfields", C.c_uint32), ("block_bytes", C.c_uint64),
                 ("field_bytes", C.c_uint32 * MAX_FIELDS), ("field_offset", C.c_uint32 * MAX_FIELDS)]
+
+
+class CtorNone(C.Structure):
+    _fields_ = [("ref_out", C.c_void_p)]
 
 
 class CtorArrays(C.Structure):
@@ -116,6 +122,8 @@ def lib():
             "smmo_parallel_new": ([P, u32, u64, u32, P, u64, P], i),
             "smmo_parallel_alloc": ([P, u32, u64, u32, u32, P, u64, P], i),
             "smmo_parallel_do": ([P, u32, u32, P, u64, P], i),
+            "smmo_parallel_destroy": ([P, P, u64, u32, P], i),
+            "smmo_occupancy": ([P, P, P, P, P], i),
             "smmo_live_count": ([P, u32, P, P], i),
             "smmo_dump_objects": ([P, u32, P, u64, P, P], i),
             "smmo_dump_refs": ([P, u32, P, u64, P, P], i),
@@ -260,6 +268,19 @@ class Heap:
         p, nb = _blob(args)
         check(lib().smmo_parallel_alloc(self.h, cls, nthreads, per_thread, ctor, p, nb, _stream(stream)))
 
+    def parallel_destroy(self, refs, nthreads: int, per_thread: int = 1, stream=None) -> None:
+        """Thread t destroys refs[t*per_thread + k], k < per_thread (device uint64 tensor)."""
+        assert refs.numel() >= nthreads * per_thread and refs.element_size() == 8 and refs.is_contiguous()
+        check(lib().smmo_parallel_destroy(self.h, refs.data_ptr(), nthreads, per_thread, _stream(stream)))
+
+    def occupancy(self, stream=None) -> dict:
+        """Per-class used slots, slots and blocks, and the fragmentation F (Sec. 6.3)."""
+        n = len(self.classes)
+        used, slots, blocks = (C.c_uint64 * n)(), (C.c_uint64 * n)(), (C.c_uint64 * n)()
+        check(lib().smmo_occupancy(self.h, used, slots, blocks, _stream(stream)))
+        u, sl, b = list(used), list(slots), list(blocks)
+        return {"used": u, "slots": sl, "blocks": b, "F": (1.0 - sum(u) / sum(sl)) if sum(sl) else 0.0}
+
     def parallel_do(self, cls: int, method: int, args=None, stream=None) -> None:
         p, nb = _blob(args)
         check(lib().smmo_parallel_do(self.h, cls, method, p, nb, _stream(stream)))
@@ -289,6 +310,11 @@ class Heap:
         buf = np.zeros(nb.value, dtype=np.uint8)
         check(lib().smmo_dump_raw(self.h, buf.ctypes.data, nb.value, _stream(stream)))
         return buf.tobytes()
+
+
+def ctor_none(ref_out=None) -> CtorNone:
+    """Argument blob of CTOR_NONE: object memory untouched, handle i -> ref_out[i]."""
+    return CtorNone(None if ref_out is None else ref_out.data_ptr())
 
 
 def ctor_arrays(srcs, ref_out=None, ref_index=None) -> CtorArrays:

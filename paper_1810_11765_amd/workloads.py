@@ -58,6 +58,39 @@ class AllocBench:
         return ids[o], x[o], v[o]
 
 
+class LinuxScalability:
+    """Raw allocation benchmark (Sec. 6.4): one class of 64-byte objects
+    (eight 8-byte fields, N = 64, 4 KiB blocks) in a heap whose whole device
+    footprint is `heap_total` bytes; `nthreads` threads each allocate n
+    objects without touching them, a second kernel destroys them."""
+
+    CLASSES = [[8] * 8]
+
+    def __init__(self, nthreads=16384, heap_total=1 << 30, max_per_thread=1024, device="cuda"):
+        self.nthreads = nthreads
+        # the most blocks whose heap (metadata + scratch + data) fits heap_total
+        lo, hi = 1, heap_total // 4096 + 1
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if S.heap_bytes(self.CLASSES, mid) <= heap_total:
+                lo = mid
+            else:
+                hi = mid - 1
+        self.num_blocks = lo
+        self.heap = S.Heap(self.CLASSES, lo, device=device)
+        self.refs = torch.zeros(nthreads * max_per_thread, dtype=torch.int64, device=device)
+        self._args = S.ctor_none(self.refs)
+
+    def alloc(self, n: int, stream=None):
+        self.heap.parallel_alloc(0, self.nthreads, n, S.CTOR_NONE, self._args, stream=stream)
+
+    def free(self, n: int, stream=None):
+        self.heap.parallel_destroy(self.refs, self.nthreads, n, stream=stream)
+
+    def data_bytes(self) -> int:
+        return self.num_blocks * 64 * 64
+
+
 class LifeGrid:
     """Life-like grid: Cell {int32 x, int32 y, int8 alive} (class 0) and
     Agent {int32 cell, int32 age} (class 1) on a width x height torus."""

@@ -33,3 +33,15 @@ def bits_equal(a: np.ndarray, b: np.ndarray) -> bool:
     if a.shape != b.shape:
         return False
     return np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def wator_check(w, steps_done, oracle_state):
+    """Predator-prey state of workload `w` equals the oracle's (bit-exact),
+    the occupancy grid agrees with the live objects, and the heap is sound."""
+    kind, age, energy = w.state()
+    ok, oa, oe = oracle_state
+    assert np.array_equal(kind, ok), f"occupancy differs after {steps_done} steps"
+    assert np.array_equal(age[kind > 0], oa[ok > 0]), f"ages differ after {steps_done} steps"
+    assert np.array_equal(energy[kind == 2], oe[ok == 2]), f"energies differ after {steps_done} steps"
+    assert np.array_equal(w.occ_kind(), kind), "occupancy grid disagrees with the live objects"
+    return check_heap(w.heap, expect_live=[int((ok == 1).sum()), int((ok == 2).sum())])

@@ -4,7 +4,7 @@ workloads: bit-exact."""
 import numpy as np
 import pytest
 
-from helpers import check_heap, say
+from helpers import check_heap, say, wator_check as _wator_check
 from oracle import core
 from paper_1810_11765_amd import inputs
 
@@ -72,16 +72,6 @@ def test_life_textbook_glider_on_gpu():
     for x, y in [(2, 1), (3, 2), (1, 3), (2, 3), (3, 3)]:
         want[y * W_ + x] = 1
     assert np.array_equal(alive, want)
-
-
-def _wator_check(w, steps_done, oracle_state):
-    kind, age, energy = w.state()
-    ok, oa, oe = oracle_state
-    assert np.array_equal(kind, ok), f"occupancy differs after {steps_done} steps"
-    assert np.array_equal(age[kind > 0], oa[ok > 0]), f"ages differ after {steps_done} steps"
-    assert np.array_equal(energy[kind == 2], oe[ok == 2]), f"energies differ after {steps_done} steps"
-    assert np.array_equal(w.occ_kind(), kind), "occupancy grid disagrees with the live objects"
-    check_heap(w.heap, expect_live=[int((ok == 1).sum()), int((ok == 2).sum())])
 
 
 @pytest.mark.parametrize("seed", [42, 7, 1234])

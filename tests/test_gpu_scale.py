@@ -1,0 +1,144 @@
+"""GPU tests of the allocator's measurement paths through the C-ABI:
+
+* big heaps, where the do-all, the iteration snapshot and the live count go
+  through level 1 of the allocated bitmap (Sec. 6.5) -- predator-prey results
+  bit-exact against the oracle with and without that skip;
+* the allocator variants of the ablations (no rotation, no request
+  coalescing, r = 1..8 lookups, Sec. 6.3) -- placement changes, results do
+  not;
+* the occupancy / fragmentation query against the raw-dump checker;
+* raw allocation without constructor and device-side destroy by handle
+  (the raw allocation benchmark of Sec. 6.4).
+"""
+import numpy as np
+import pytest
+
+from helpers import check_heap, say, wator_check
+from oracle import core, heapcheck
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def S():
+    from paper_1810_11765_amd import smmo
+    return smmo
+
+
+def W():
+    from paper_1810_11765_amd import workloads
+    return workloads
+
+
+def _occupancy_matches_dump(heap, summary):
+    occ = heap.occupancy()
+    raw = heapcheck.RawHeap(heap.dump_raw())
+    assert occ["used"] == summary["live"]
+    assert occ["blocks"] == summary["blocks"]
+    assert occ["slots"] == [b * heap.capacity(t) for t, b in enumerate(summary["blocks"])]
+    assert abs(occ["F"] - heapcheck.fragmentation(raw)) < 1e-12
+    return occ
+
+
+# 270,000 blocks: 4,219 level-0 words, above the word-list threshold of 4,096
+@pytest.mark.parametrize("flat", [False, True])
+def test_wator_big_heap_parity(flat):
+    say("wator big heap", "flat" if flat else "word list")
+    w = W().WaTor(seed=11, width=193, height=97, num_blocks=270_000)
+    if flat:
+        w.heap.set_tuning(S().TUNE_FLAT_ENUM)
+    w.populate()
+    for s in range(1, 81):
+        w.step()
+        if s in (1, 80):
+            summary = wator_check(w, s, core.c3_run(w.kind0, 193, 97, 11, s))
+    _occupancy_matches_dump(w.heap, summary)
+
+
+VARIANTS = [("default", 0, 5), ("noshift", 1, 5), ("nocoal", 2, 5), ("nocoal-noshift", 3, 5),
+            ("r1", 0, 1), ("r2", 0, 2), ("r3", 0, 3), ("r8", 0, 8)]
+
+
+@pytest.mark.parametrize("name,flags,lookups", VARIANTS, ids=[v[0] for v in VARIANTS])
+def test_wator_allocator_variants_parity(name, flags, lookups):
+    say("wator variant", name)
+    w = W().WaTor(seed=21, width=160, height=144, num_blocks=1024)
+    w.heap.set_tuning(flags, lookups)
+    w.populate()
+    for _ in range(60):
+        w.step()
+    summary = wator_check(w, 60, core.c3_run(w.kind0, 160, 144, 21, 60))
+    occ = _occupancy_matches_dump(w.heap, summary)
+    assert 0.0 <= occ["F"] < 1.0
+
+
+def _aligned_heap(classes, num_blocks, fill):
+    nbytes = S().heap_bytes(classes, num_blocks)
+    buf = torch.full((nbytes + 4096,), fill, dtype=torch.uint8, device="cuda")
+    base = buf.data_ptr() + (-buf.data_ptr()) % 256
+    return buf, S().Heap(classes, num_blocks, dev_ptr=base)
+
+
+def test_raw_alloc_untouched_then_destroy_by_handle():
+    say("raw alloc / destroy")
+    classes = [[8] * 8]                                   # one 64-byte class, N = 64
+    buf, h = _aligned_heap(classes, 64, 0xAB)
+    nthreads, per = 1000, 3                               # ragged last wave
+    refs = torch.zeros(nthreads * per, dtype=torch.int64, device="cuda")
+    h.parallel_alloc(0, nthreads, per, S().CTOR_NONE, S().ctor_none(refs))
+    r = refs.cpu().numpy().view(np.uint64)
+    assert (r != 0).all() and np.unique(r).size == r.size
+    assert (S().ref_class(r) == 0).all()
+    summary = check_heap(h, expect_live=[nthreads * per])
+    fields = h.dump_objects(0, [np.uint64] * 8)
+    assert all((f == np.uint64(0xABABABABABABABAB)).all() for f in fields), "object memory was written"
+    _occupancy_matches_dump(h, summary)
+    h.parallel_destroy(refs, nthreads, per)
+    summary = check_heap(h, expect_live=[0])
+    assert summary["free"] == 64 and summary["blocks"] == [0]
+    h.close()
+    del buf
+
+
+def test_raw_alloc_oom_gives_null_handles():
+    say("raw alloc oom")
+    classes = [[8] * 8]
+    buf, h = _aligned_heap(classes, 8, 0)                 # 512 slots
+    nthreads, per = 300, 2                                # 600 requests
+    refs = torch.zeros(nthreads * per, dtype=torch.int64, device="cuda")
+    h.parallel_alloc(0, nthreads, per, S().CTOR_NONE, S().ctor_none(refs))
+    assert h.status() & S().STATUS_OOM
+    r = refs.cpu().numpy().view(np.uint64)
+    got = r[r != 0]
+    assert np.unique(got).size == got.size
+    assert got.size == 512, "every slot of the heap is handed out before OOM"
+    h.clear_status()
+    check_heap(h, expect_live=[512])
+    assert h.occupancy()["F"] == 0.0
+    h.parallel_destroy(refs, nthreads, per)             # null handles are skipped
+    summary = check_heap(h, expect_live=[0])
+    assert summary["free"] == 8
+    h.close()
+    del buf
+
+
+def test_raw_alloc_full_size_then_destroy():
+    """16,384 threads x 64 objects of 64 B in a 1 GiB heap, then destroy all."""
+    say("raw alloc 16384 x 64")
+    ls = W().LinuxScalability()
+    ls.alloc(64)
+    assert ls.heap.status() == 0
+    assert ls.heap.live_count(0) == 16384 * 64
+    r = ls.refs[: 16384 * 64].cpu().numpy().view(np.uint64)
+    assert (r != 0).all() and np.unique(r).size == r.size
+    ls.free(64)
+    assert ls.heap.live_count(0) == 0
+    occ = ls.heap.occupancy()
+    assert occ["blocks"] == [0] and ls.heap.status() == 0
