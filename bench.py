@@ -307,9 +307,11 @@ def ablation_suite(torch, workloads, steps):
                 F.append(round(w.heap.occupancy()["F"], 5))
         torch.cuda.synchronize()
         ms = tm.ms("step")
+        st = w.heap.stats()
         out[name] = {"flags": flags, "lookups": lookups, "ms_per_step": round(sum(ms) / len(ms), 5),
-                     "ms_total": round(sum(ms), 3), "F_every_10_steps": F,
+                     "ms_total": round(sum(ms), 3), "ms_max_step": round(max(ms), 3), "F_every_10_steps": F,
                      "F_mean_last_100": round(sum(F[-10:]) / len(F[-10:]), 5), "status": w.heap.status(),
+                     "guards": {k: st[k] for k in ("guard_alloc", "guard_spin", "guard_inval", "oom")},
                      "_w": w}
     _progress("ablation oracle")
     ref = core.c3_run(kind0, side, side, seed, steps)
@@ -378,23 +380,29 @@ def blocks_for_bytes(classes, total: int) -> int:
 
 
 def heap_size_suite(torch, workloads, steps):
-    """Predator-prey 1024 x 1024 (seed 42) in heaps of 1 to 64 GiB (Sec. 6.5):
-    step time with the level-1 skip (default) and with every level-0 word
-    scanned (flat), and whether the final state equals the oracle's."""
+    """Predator-prey 1024 x 1024 (seed 42) in its own 32,768-block heap and in
+    heaps of 1 to 64 GiB (Sec. 6.5): step time with the level-1 skip
+    (default; a heap under 4,096 level-0 words is always scanned flat), with
+    every level-0 word scanned (flat), and with new blocks taken anywhere in
+    the heap (spread: free-block search rotated at every level), and whether
+    the final state equals the oracle's."""
     from oracle import core
     from paper_1810_11765_amd import smmo as S
     seed, side = 42, 1024
     kind0 = None
     rows = []
-    for gib in (1, 2, 4, 8, 16, 32, 64):
-        nb = blocks_for_bytes(workloads.WaTor.CLASSES, gib << 30)
+    for gib in (0, 1, 2, 4, 8, 16, 32, 64):
+        # 0: the workload's own 32,768-block heap (25 MiB), the reference row
+        nb = 32768 if gib == 0 else blocks_for_bytes(workloads.WaTor.CLASSES, gib << 30)
         row = {"heap_gib": gib, "num_blocks": nb}
-        for mode in ("hierarchical", "flat"):
+        for mode in ("hierarchical", "flat", "spread"):
             _progress("heap-size", gib, mode)
             w = workloads.WaTor(seed=seed, width=side, height=side, num_blocks=nb, kind0=kind0)
             kind0 = w.kind0
             if mode == "flat":
                 w.heap.set_tuning(S.TUNE_FLAT_ENUM, 5, 0)
+            elif mode == "spread":
+                w.heap.set_tuning(S.TUNE_FREE_SPREAD, 5, 0)
             w.populate()
             tm = Timer(torch)
             for _ in range(steps):
@@ -402,9 +410,9 @@ def heap_size_suite(torch, workloads, steps):
             torch.cuda.synchronize()
             ms = tm.ms("step")
             row[mode] = {"ms_per_step": round(sum(ms) / len(ms), 5), "status": w.heap.status(), "_w": w}
-            if mode == "hierarchical":
+            if mode != "flat":
                 row[mode]["F_end"] = round(w.heap.occupancy()["F"], 5)
-            if gib == 1 and mode == "hierarchical":
+            if gib == 0 and mode == "hierarchical":
                 _progress("heap-size oracle")
                 ref = core.c3_run(kind0, side, side, seed, steps)
             row[mode]["identical_to_oracle"] = _wator_same(w, ref)

@@ -48,10 +48,19 @@ extern "C" {
 
 /* ------------------------------------------------------------- types ---- */
 
-/* One class: its fields' byte sizes in declaration order (each 1, 2, 4 or 8). */
+/* One class: the byte sizes of the fields it introduces, in declaration
+ * order (each 1, 2, 4 or 8), and its direct superclass.  A subclass's objects
+ * hold the superclass's fields first (inherited, same field indices), then
+ * its own (Sec. 3.2: inherited SOA arrays first), so a method written for a
+ * class runs unchanged on its subclasses.  A subclass may introduce no field
+ * (nfields 0, field_bytes NULL); every class has 1..SMMO_MAX_FIELDS fields
+ * in all.  Blocks hold objects of exactly one class; allocated[T] and
+ * active[T] index T's own blocks only (Sec. 3.4). */
 typedef struct smmo_class_desc {
     uint32_t nfields;
     const uint8_t* field_bytes;   /* host array of nfields sizes */
+    uint32_t superclass;          /* 0: none; else 1 + the superclass's id, which
+                                     must be smaller than this class's id */
 } smmo_class_desc;
 
 /* Layout of one class inside a block (Sec. 3.2; SOA arrays 128-B aligned). */
@@ -107,6 +116,7 @@ typedef struct smmo_raw_header {
     uint32_t lookups;                        /* active-block lookup attempts r (Sec. 4.2) */
     uint32_t force_fail_ppm;                 /* fault injection rate of try_find_set */
     uint32_t reserved0;
+    uint32_t superclass[SMMO_MAX_CLASSES];   /* as in smmo_class_desc (0: none) */
 } smmo_raw_header;
 
 /* Device counters (SMMO_TUNE_STATS), uint64 at off_status + 64. */
@@ -121,6 +131,11 @@ enum smmo_counter {
     SMMO_CNT_RESERVE_FAIL,      /* reservations that got no slot */
     SMMO_CNT_SPIN,              /* retries of spinning set/clear */
     SMMO_CNT_RESERVE_ATOMIC,    /* atomic ORs on allocation bitmaps */
+    /* the next four are counted whether or not SMMO_TUNE_STATS is set */
+    SMMO_CNT_GUARD_ALLOC,       /* allocations abandoned at the retry bound (SMMO_STATUS_RETRY) */
+    SMMO_CNT_GUARD_SPIN,        /* bitmap set/clear spins abandoned at their bound (SMMO_STATUS_RETRY) */
+    SMMO_CNT_GUARD_INVAL,       /* invalidations abandoned at their bound (SMMO_STATUS_RETRY) */
+    SMMO_CNT_OOM,               /* wave allocation requests that ended in OOM */
     SMMO_CNT_NUM = 16
 };
 
@@ -133,6 +148,8 @@ enum smmo_counter {
                                        reserving in it (widens the race window of App. A.3) */
 #define SMMO_TUNE_FLAT_ENUM 32u     /* do-all, snapshot and live count scan every level-0
                                        word even in big heaps (no level-1 skip) */
+#define SMMO_TUNE_FREE_SPREAD 64u   /* free-block search rotated at every bitmap level (new
+                                       blocks anywhere in the heap); default: the two lowest */
 
 /* -------------------------------------------------- heap management ---- */
 
@@ -347,7 +364,13 @@ int smmo_parallel_destroy(smmo_heap* heap, const uint64_t* refs, uint64_t nthrea
                           void* stream);
 
 /* parallel_do<T, method> (Sec. 2.1, Sec. 3.7): run `method_id` on every live
- * object of class `cls`.  args: the method's blob (<= SMMO_ARGS_MAX bytes). */
+ * object of class `cls` and of its subclasses (transitively), one kernel per
+ * class in ascending class id.  Objects the method creates, in any of these
+ * classes, are not visited by the same call: with subclasses, the iteration
+ * words of every class are taken before the first kernel.  A method destroys
+ * no object of these classes other than the one it runs on.  The n-body
+ * methods take a class without subclasses.  args: the method's blob
+ * (<= SMMO_ARGS_MAX bytes). */
 int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
                      uint64_t args_bytes, void* stream);
 

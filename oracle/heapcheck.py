@@ -61,6 +61,8 @@ class RawHeap:
         self.field_bytes = fb.reshape(MAX_CLASSES, MAX_FIELDS)[: self.ncls]
         self.field_off = fo.reshape(MAX_CLASSES, MAX_FIELDS)[: self.ncls]
         self.tune_flags, self.lookups, self.force_fail_ppm = struct.unpack_from("<III", b, 2528)
+        # 1 + superclass id per class (0: none)
+        self.superclass = list(struct.unpack_from("<16I", b, 2544))[: self.ncls]
         M = self.M
         self.status = struct.unpack_from("<I", b, self.off_status)[0]
         self.counters = np.frombuffer(b, dtype="<u8", count=16, offset=self.off_status + 64)

@@ -15,6 +15,16 @@ def align(v: int, a: int) -> int:
     return (v + a - 1) // a * a
 
 
+def flatten(specs):
+    """Full field lists of classes given as (own field sizes, superclass id or
+    None): a subclass's objects hold the superclass's fields first, then its
+    own (Sec. 3.2, the data segment starts with the inherited SOA arrays)."""
+    out = []
+    for own, sup in specs:
+        out.append((list(out[sup]) if sup is not None else []) + list(own))
+    return out
+
+
 def capacity(classes, t: int) -> int:
     sizes = [sum(c) for c in classes]
     n = (64 * min(sizes)) // sizes[t]

@@ -25,8 +25,13 @@
 
 namespace smmo {
 
+// Bounds of the allocator's retry loops.  A wave gives up an allocation
+// after kOomRounds consecutive rounds that find neither an active nor a free
+// block (OOM), or after kAllocIters iterations in all (RETRY: a livelock
+// guard that contention alone does not reach).  Once the status word holds
+// OOM or RETRY, later requests give up after a few rounds instead.
 constexpr uint32_t kOomRounds = 4096;
-constexpr uint32_t kAllocIters = 1u << 14;
+constexpr uint32_t kAllocIters = 1u << 18;
 
 // initialize_block<T> (Alg. 8): type first, then (after a release) the words.
 // The iteration word is zeroed as well, so a block re-initialized during a
@@ -57,7 +62,7 @@ __device__ inline bool invalidate_block(const DevHeap& h, uint64_t bid) {
         if ((before_rb & before) != pad) return false;
         // emptied again while invalidated: try once more
     }
-    set_status(h, SMMO_STATUS_RETRY);
+    guard_hit(h, SMMO_CNT_GUARD_INVAL, SMMO_STATUS_RETRY);
     return false;
 }
 
@@ -89,9 +94,10 @@ __device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t 
     if (h.tune & SMMO_TUNE_NO_COALESCE) want = 1;
     for (uint32_t iters = 0;; ++iters) {
         if (iters > kAllocIters) {                        // livelock guard: never hang a kernel
-            set_status(h, SMMO_STATUS_RETRY);
+            guard_hit(h, SMMO_CNT_GUARD_ALLOC, SMMO_STATUS_RETRY);
             return 0;
         }
+        if (iters >= 64 && (iters & 63) == 0 && status_has(h, SMMO_STATUS_RETRY)) return 0;
         uint64_t bid = kFail;
         for (uint32_t a = 0; a < h.lookups; ++a) {
             seed = splitmix64(seed);
@@ -100,10 +106,11 @@ __device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t 
             count(h, SMMO_CNT_FIND_FAIL);
         }
         if (bid == kFail) {                               // slow path
-            bid = bm_clear_any(h, bm_free(), seed);
+            bid = bm_clear_any(h, bm_free(), seed,
+                               (h.tune & SMMO_TUNE_FREE_SPREAD) ? SMMO_MAX_LEVELS : kFreeRotLevels);
             if (bid == kFail) {
-                if (++empty_rounds > kOomRounds) {
-                    set_status(h, SMMO_STATUS_OOM);
+                if (++empty_rounds > kOomRounds || (empty_rounds > 2 && status_has(h, SMMO_STATUS_OOM))) {
+                    guard_hit(h, SMMO_CNT_OOM, SMMO_STATUS_OOM);
                     return 0;
                 }
                 backoff();

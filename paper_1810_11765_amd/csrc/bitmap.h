@@ -10,14 +10,16 @@
 // leader); a spin here never waits on another lane of its own wave, which a
 // wave64 could not schedule (lanes of a wave share one program counter).
 // Every spin is bounded: past kSpinLimit it raises SMMO_STATUS_RETRY and gives
-// up, so a kernel always terminates even on a corrupted heap.
+// up, so a kernel always terminates even on a corrupted heap; once the status
+// word holds RETRY (the run is already invalid) spins give up early, so the
+// kernel ends soon after the first bound is hit.
 #pragma once
 
 #include "dev.h"
 
 namespace smmo {
 
-constexpr uint32_t kSpinLimit = 1u << 16;
+constexpr uint32_t kSpinLimit = 1u << 18;
 
 __device__ inline uint64_t* bm_word(const DevHeap& h, uint32_t b, uint32_t level, uint64_t idx) {
     return h.bm + (uint64_t)b * h.bitmap_words + h.level_off[level] + idx;
@@ -32,7 +34,8 @@ __device__ inline void bm_set_from(const DevHeap& h, uint32_t b, uint32_t level,
         uint64_t prev = at_or(w, bit);
         uint32_t spins = 0;
         while (prev & bit) {
-            if (++spins > kSpinLimit) { set_status(h, SMMO_STATUS_RETRY); return; }
+            if (++spins > kSpinLimit) { guard_hit(h, SMMO_CNT_GUARD_SPIN, SMMO_STATUS_RETRY); return; }
+            if ((spins & 255) == 0 && status_has(h, SMMO_STATUS_RETRY)) return;
             count(h, SMMO_CNT_SPIN);
             backoff();
             prev = at_or(w, bit);
@@ -50,7 +53,8 @@ __device__ inline void bm_clear_from(const DevHeap& h, uint32_t b, uint32_t leve
         uint64_t prev = at_and(w, ~bit);
         uint32_t spins = 0;
         while (!(prev & bit)) {
-            if (++spins > kSpinLimit) { set_status(h, SMMO_STATUS_RETRY); return; }
+            if (++spins > kSpinLimit) { guard_hit(h, SMMO_CNT_GUARD_SPIN, SMMO_STATUS_RETRY); return; }
+            if ((spins & 255) == 0 && status_has(h, SMMO_STATUS_RETRY)) return;
             count(h, SMMO_CNT_SPIN);
             backoff();
             prev = at_and(w, ~bit);
@@ -81,7 +85,10 @@ __device__ inline uint32_t rot_ffs(uint64_t w, uint32_t rot) {
 
 // try_find_set() (Alg. 4), top-down from the single top word.  `seed` gives a
 // different rotation per level; it depends on the wave and changes per retry.
-__device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_t seed) {
+// Levels at or above `rot_levels` take the first set bit instead (levels
+// counted from 0 = the block level).
+__device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_t seed,
+                                           uint32_t rot_levels = SMMO_MAX_LEVELS) {
     if ((h.tune & SMMO_TUNE_FORCE_FAIL) && (uint32_t)(splitmix64(seed) % 1000000u) < h.force_fail_ppm)
         return kFail;
     const bool rotate = !(h.tune & SMMO_TUNE_NO_ROTATE);
@@ -89,17 +96,25 @@ __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_
     for (int l = (int)h.nlevels - 1; l >= 0; --l) {
         uint64_t w = at_load(bm_word(h, b, (uint32_t)l, idx));
         if (!w) return kFail;
-        uint32_t bit = rotate ? rot_ffs(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
+        uint32_t bit = rotate && (uint32_t)l < rot_levels ? rot_ffs(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
         idx = (idx << 6) | bit;
     }
     return idx;
 }
 
+// Rotated levels of the free-block search: the two lowest, so concurrent
+// slow paths spread over the 4,096 blocks under one level-2 bit while new
+// blocks are taken from the low end of the heap (the class's blocks stay
+// close together in big heaps: fewer pages and bitmap words to visit).
+// SMMO_TUNE_FREE_SPREAD rotates every level instead.
+constexpr uint32_t kFreeRotLevels = 2;
+
 // clear(): find and clear any set bit; kFail if a lookup finds none.
-__device__ inline uint64_t bm_clear_any(const DevHeap& h, uint32_t b, uint64_t& seed) {
+__device__ inline uint64_t bm_clear_any(const DevHeap& h, uint32_t b, uint64_t& seed,
+                                        uint32_t rot_levels = SMMO_MAX_LEVELS) {
     for (uint32_t tries = 0; tries < 64; ++tries) {
         seed = splitmix64(seed);
-        uint64_t i = bm_try_find_set(h, b, seed);
+        uint64_t i = bm_try_find_set(h, b, seed, rot_levels);
         if (i == kFail) return kFail;
         if (bm_try_clear(h, b, i)) return i;
     }

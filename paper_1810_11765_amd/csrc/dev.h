@@ -87,6 +87,14 @@ __device__ inline void count(const DevHeap& h, uint32_t which, uint64_t n = 1) {
         __hip_atomic_fetch_add(&h.counters[which], (unsigned long long)n, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
 }
+// A bound was hit: count it (always) and raise `bits` in the status word.
+__device__ inline void guard_hit(const DevHeap& h, uint32_t which, uint32_t bits) {
+    __hip_atomic_fetch_add(&h.counters[which], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    set_status(h, bits);
+}
+__device__ inline bool status_has(const DevHeap& h, uint32_t bits) {
+    return (__hip_atomic_load(h.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bits) != 0;
+}
 __device__ inline void backoff() { __builtin_amdgcn_s_sleep(2); }
 
 // ---------------------------------------------------------- wave prims ----

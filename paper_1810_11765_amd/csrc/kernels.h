@@ -58,55 +58,58 @@ __global__ void k_fill_u64(unsigned long long* p, uint64_t n, uint64_t v) {
 }
 
 // ------------------------------------------- hierarchical enumeration ----
-// Indices of the non-empty level-0 words of bitmap `bmid`, found through
-// level 1 (Alg. 5 / Sec. 4.1.5: containers whose nested bit is clear are never
-// read), appended in any order to words[]; *count must be 0 on entry.  One
-// thread per level-1 word.  Used for big heaps so that a do-all costs the
-// occupied part of the heap, not its size (Sec. 6.5).
-__global__ void k_enum_words(DevHeap h, uint32_t bmid, uint32_t* words, unsigned long long* count) {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t w1 = 0;
-    if (j < h.level_words[1]) w1 = *bm_word(h, bmid, 1, j);
-    const uint32_t n = popc64(w1);
-    // one counter update per wave: exclusive prefix of n inside the wave
-    uint32_t incl = n;
+// Block ids of every set bit of bitmap `bmid`, found through level 1 (Alg. 5 /
+// Sec. 4.1.5: level-0 words whose level-1 bit is clear are never read),
+// appended in any order to R[]; *count must be 0 on entry.  One wave per
+// level-1 word, lane l reading child word 64j + l.  Used for big heaps so that
+// a do-all costs the class's blocks, not the heap's size (Sec. 6.5).
+__global__ __launch_bounds__(256) void k_enum_blocks(DevHeap h, uint32_t bmid, uint32_t* R,
+                                                     unsigned long long* count) {
+    const uint64_t j = global_wave();
+    const uint32_t lane = lane_id();
+    if (j >= h.level_words[1]) return;                    // wave-uniform
+    const uint64_t w1 = *bm_word(h, bmid, 1, j);
+    const uint64_t child = (j << 6) | lane;
+    uint64_t w0 = 0;
+    if ((w1 >> lane) & 1) w0 = *bm_word(h, bmid, 0, child);
+    const uint32_t n = popc64(w0);
+    uint32_t incl = n;                                    // inclusive prefix of n in the wave
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         uint32_t y = __shfl_up(incl, o, 64);
-        if (lane_id() >= (uint32_t)o) incl += y;
+        if (lane >= (uint32_t)o) incl += y;
     }
     const uint32_t total = __shfl(incl, 63, 64);
+    if (!total) return;                                   // wave-uniform
     unsigned long long base = 0;
-    if (lane_id() == 63 && total) base = atomicAdd(count, (unsigned long long)total);
+    if (lane == 63) base = atomicAdd(count, (unsigned long long)total);
     base = __shfl(base, 63, 64);
     uint64_t pos = base + incl - n;
-    while (w1) {
-        words[pos++] = (uint32_t)((j << 6) | ctz64(w1));
-        w1 &= w1 - 1;
+    while (w0) {
+        R[pos++] = (uint32_t)((child << 6) | ctz64(w0));
+        w0 &= w0 - 1;
     }
 }
 
 // --------------------------------------------------- iteration snapshot ----
 // iter <- alloc (without padding) for every allocated block of `cls`, before
 // a do-all whose method may create objects of its own class (Sec. 3.1).
-// Direct form: one thread per block.  List form (big heaps): one wave per
-// non-empty level-0 word of allocated[cls], lane = block of that word.
-__global__ void k_snapshot(DevHeap h, uint32_t cls, const uint32_t* words, const unsigned long long* nwords) {
+// Direct form: one thread per block.  List form (big heaps): one thread per
+// block of the list k_enum_blocks wrote.
+__global__ void k_snapshot(DevHeap h, uint32_t cls, const uint32_t* R, const unsigned long long* nR) {
     const uint64_t valid = ~h.cls_pad[cls];
-    if (!words) {
-        uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (b >= h.M) return;
-        uint64_t w = *bm_word(h, bm_allocated(cls), 0, b >> 6);
-        if ((w >> (b & 63)) & 1) h.iter[b] = h.alloc[b] & valid;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!R) {
+        if (i >= h.M) return;
+        uint64_t w = *bm_word(h, bm_allocated(cls), 0, i >> 6);
+        if ((w >> (i & 63)) & 1) h.iter[i] = h.alloc[i] & valid;
         return;
     }
-    const uint64_t n = *nwords;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t e = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < n; e += nwaves) {
-        const uint64_t wi = words[e];
-        const uint64_t w = *bm_word(h, bm_allocated(cls), 0, wi);
-        const uint64_t b = (wi << 6) | lane_id();
-        if ((w >> lane_id()) & 1) h.iter[b] = h.alloc[b] & valid;
+    const uint64_t n = *nR;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = i; e < n; e += stride) {
+        const uint64_t b = R[e];
+        h.iter[b] = h.alloc[b] & valid;
     }
 }
 
@@ -134,12 +137,17 @@ struct Obj {
 // iteration word written by k_snapshot (blocks initialized meanwhile have it
 // zeroed), otherwise no object of the class can appear during the do-all and
 // the allocation word itself is the snapshot.
-// With a word list (big heaps, from k_enum_words) unit u covers part of L0
-// word words[u >> s_log2] and the unit count is taken from the list length.
-template <class M>
+// With a block list (big heaps, from k_enum_blocks) a unit is a run of list
+// entries instead: lane l loads entry l of the run and that block's word, and
+// the wave then walks the run; the run length grows with the list so that
+// there are at most 16,384 units.
+// kSnap: read the iteration words of k_snapshot (always so when the do-all
+// covers a class and its subclasses, whose methods may create objects of any
+// of them).
+template <class M, bool kSnap = M::kSnapshot>
 __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls, uint32_t s_log2,
-                                                          uint64_t nunits, const uint32_t* words,
-                                                          const unsigned long long* nwords, typename M::Args a) {
+                                                          uint64_t nunits, const uint32_t* R,
+                                                          const unsigned long long* nR, typename M::Args a) {
     const uint32_t lane = lane_id();
     const uint64_t wave = global_wave();
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -148,14 +156,40 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls
     const uint32_t span = 64u >> s_log2;
     const uint64_t span_mask = span == 64 ? kOnes : ((1ull << span) - 1);
     const typename M::Prep prep = M::prepare(h, cls, a);
-    if (words) nunits = (uint64_t)*nwords << s_log2;
+    if (R) {
+        const uint64_t n = *nR;
+        uint32_t rl = 0;                                  // run length 1 << rl
+        while (rl < 6 && (n >> rl) > 16384) ++rl;
+        const uint64_t runs = (n + (1ull << rl) - 1) >> rl;
+        for (uint64_t u = wave; u < runs; u += nwaves) {
+            const uint64_t e0 = u << rl;
+            const uint32_t len = n - e0 < (1ull << rl) ? (uint32_t)(n - e0) : (1u << rl);
+            uint64_t my_blk = 0, my_word = 0;
+            if (lane < len) {
+                my_blk = R[e0 + lane];
+                // a listed block stays allocated to the class, and its
+                // iteration word unchanged, until its own wave has visited it
+                // (a method destroys only its own object), so the word is
+                // read right away
+                my_word = kSnap ? h.iter[my_blk] : h.alloc[my_blk];
+            }
+            for (uint32_t k = 0; k < len; ++k) {
+                const uint64_t bid = (uint64_t)__shfl((unsigned long long)my_blk, (int)k, 64);
+                const uint64_t live = (uint64_t)__shfl((unsigned long long)my_word, (int)k, 64) & valid;
+                Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
+                      wave_seed(wave, bid)};
+                M::run(o, prep, a);
+            }
+        }
+        return;
+    }
     for (uint64_t u = wave; u < nunits; u += nwaves) {
-        const uint64_t w = words ? (uint64_t)words[u >> s_log2] : u >> s_log2;
+        const uint64_t w = u >> s_log2;
         const uint32_t first = (uint32_t)(u & ((1u << s_log2) - 1)) * span;   // first block bit of the unit
         const uint64_t my_blk = (w << 6) + first + lane;                       // lane l: block first + l
         const bool mine = lane < span && my_blk < h.M;
         uint64_t my_word = 0, word;
-        if (!M::kSnapshot) {
+        if (!kSnap) {
             // The class gains no block during this do-all and a block leaves
             // only through its own wave, so the words can be fetched together
             // with the bitmap word; words of blocks whose bit is clear are
@@ -284,24 +318,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_destroy(DevHeap h, const uint
 
 // ------------------------------------------------------------ counting ----
 // Live objects of `cls` -> *out (added).  Direct form: one thread per block;
-// list form: one wave per listed L0 word of allocated[cls].
-__global__ void k_live_count(DevHeap h, uint32_t cls, const uint32_t* words, const unsigned long long* nwords,
+// list form: one thread per listed block.
+__global__ void k_live_count(DevHeap h, uint32_t cls, const uint32_t* R, const unsigned long long* nR,
                              unsigned long long* out) {
     uint32_t c = 0;
-    if (!words) {
-        uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (b < h.M) {
-            uint64_t w = *bm_word(h, bm_allocated(cls), 0, b >> 6);
-            if ((w >> (b & 63)) & 1) c = popc64(h.alloc[b] & ~h.cls_pad[cls]);
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!R) {
+        if (i < h.M) {
+            uint64_t w = *bm_word(h, bm_allocated(cls), 0, i >> 6);
+            if ((w >> (i & 63)) & 1) c = popc64(h.alloc[i] & ~h.cls_pad[cls]);
         }
     } else {
-        const uint64_t n = *nwords;
-        const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-        for (uint64_t e = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < n; e += nwaves) {
-            const uint64_t wi = words[e];
-            const uint64_t w = *bm_word(h, bm_allocated(cls), 0, wi);
-            if ((w >> lane_id()) & 1) c += popc64(h.alloc[(wi << 6) | lane_id()] & ~h.cls_pad[cls]);
-        }
+        const uint64_t n = *nR;
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t e = i; e < n; e += stride) c += popc64(h.alloc[R[e]] & ~h.cls_pad[cls]);
     }
     c = wave_add(c);
     if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);

@@ -66,9 +66,10 @@ constexpr uint64_t kScratchHead = 1024;                 // bytes of scratch coun
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 inline unsigned grid_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
-// Layout of every class (Sec. 3.2): N_T = floor(64 * size(T_s) / size(T));
-// SOA arrays in declaration order, each starting on a 128-B boundary; every
-// block has the size of the largest class layout.
+// Layout of every class (Sec. 3.2): a class's fields are its superclass's
+// (inherited, first) followed by its own; N_T = floor(64 * size(T_s) /
+// size(T)); SOA arrays in field order, each starting on a 128-B boundary;
+// every block has the size of the largest class layout.
 int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_raw_header* hdr) {
     if (!cls || ncls == 0 || ncls > SMMO_MAX_CLASSES) return fail(SMMO_EINVAL, "ncls must be 1..%d", SMMO_MAX_CLASSES);
     if (M == 0 || M > (1ull << 32)) return fail(SMMO_EINVAL, "num_blocks must be 1..2^32");
@@ -76,15 +77,27 @@ int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_r
     uint64_t size[SMMO_MAX_CLASSES];
     uint64_t smin = ~0ull;
     for (uint32_t t = 0; t < ncls; ++t) {
-        if (cls[t].nfields == 0 || cls[t].nfields > SMMO_MAX_FIELDS || !cls[t].field_bytes)
-            return fail(SMMO_EINVAL, "class %u: nfields must be 1..%d", t, SMMO_MAX_FIELDS);
-        size[t] = 0;
+        const uint32_t sup = cls[t].superclass;
+        if (sup > t) return fail(SMMO_EINVAL, "class %u: superclass must be a smaller class id", t);
+        if (cls[t].nfields > SMMO_MAX_FIELDS || (cls[t].nfields && !cls[t].field_bytes))
+            return fail(SMMO_EINVAL, "class %u: nfields must be 0..%d with a field array", t, SMMO_MAX_FIELDS);
+        uint32_t nf = 0;
+        if (sup) {                                         // inherited fields first
+            nf = (uint32_t)hdr->nfields[sup - 1];
+            for (uint32_t f = 0; f < nf; ++f) hdr->field_bytes[t][f] = hdr->field_bytes[sup - 1][f];
+        }
+        if (nf + cls[t].nfields == 0 || nf + cls[t].nfields > SMMO_MAX_FIELDS)
+            return fail(SMMO_EINVAL, "class %u: 1..%d fields in all, inherited included", t, SMMO_MAX_FIELDS);
         for (uint32_t f = 0; f < cls[t].nfields; ++f) {
             uint32_t b = cls[t].field_bytes[f];
             if (b != 1 && b != 2 && b != 4 && b != 8)
                 return fail(SMMO_EINVAL, "class %u field %u: size %u not 1/2/4/8", t, f, b);
-            size[t] += b;
+            hdr->field_bytes[t][nf++] = b;
         }
+        hdr->nfields[t] = nf;
+        hdr->superclass[t] = sup;
+        size[t] = 0;
+        for (uint32_t f = 0; f < nf; ++f) size[t] += hdr->field_bytes[t][f];
         smin = std::min(smin, size[t]);
     }
     uint64_t block = 0;
@@ -92,12 +105,10 @@ int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_r
         uint64_t n = 64 * smin / size[t];
         if (n < 1) return fail(SMMO_EINVAL, "class %u is more than 64x the smallest class", t);
         hdr->capacity[t] = n;
-        hdr->nfields[t] = cls[t].nfields;
         uint64_t off = 0;
-        for (uint32_t f = 0; f < cls[t].nfields; ++f) {
-            hdr->field_bytes[t][f] = cls[t].field_bytes[f];
+        for (uint32_t f = 0; f < hdr->nfields[t]; ++f) {
             hdr->field_off[t][f] = (uint32_t)off;
-            off += align_up(n * cls[t].field_bytes[f], 128);
+            off += align_up(n * hdr->field_bytes[t][f], 128);
         }
         block = std::max(block, off);
     }
@@ -130,8 +141,8 @@ int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_r
     hdr->off_iter = p;         p = align_up(p + 8 * M, 256);
     hdr->off_bitmaps = p;      p = align_up(p + 8 * hdr->bitmap_words * (1 + 2 * (uint64_t)ncls), 256);
     hdr->off_scratch = p;
-    // counters (1 KiB), block list R (4 B per block), L0 word list (4 B per L0 word)
-    hdr->scratch_bytes = align_up(kScratchHead + 4 * M + 4 * hdr->level_words[0], 256);
+    // counters (1 KiB), then a block list R (4 B per block)
+    hdr->scratch_bytes = align_up(kScratchHead + 4 * M, 256);
     p += hdr->scratch_bytes;
     hdr->off_data = align_up(p, 4096);
     hdr->total_bytes = hdr->off_data + M * block;
@@ -190,36 +201,35 @@ unsigned long long* scratch_counter(smmo_heap* H, int i) {
     return reinterpret_cast<unsigned long long*>(H->dev.scratch) + i;
 }
 // scratch counters: 0 parallel_new's found, 1 live count, 2 n-body's found,
-// 3 word-list length, 8.. occupancy (3 per class)
+// 3 block-list length, 8.. occupancy (3 per class).  R is the block list of
+// whichever call ran last on the heap's stream (calls on one heap are
+// stream-ordered).
 uint32_t* scratch_R(smmo_heap* H) { return reinterpret_cast<uint32_t*>(H->dev.scratch + kScratchHead); }
-uint32_t* scratch_words(smmo_heap* H) {
-    return reinterpret_cast<uint32_t*>(H->dev.scratch + kScratchHead + 4 * H->hdr.num_blocks);
-}
 
 #ifndef SMMO_LIST_MIN_WORDS
 #define SMMO_LIST_MIN_WORDS 4096   // L0 words from which enumeration goes through level 1
 #endif
 
-// Big heaps: list the non-empty L0 words of allocated[cls] via level 1, so
-// that the passes after it cost the class's blocks, not the heap's size.
+// Big heaps: list the blocks of allocated[cls] via level 1 into R, so that
+// the passes after it cost the class's blocks, not the heap's size.
 // Returns false (nothing launched) when the heap is scanned flat.
-bool build_word_list(smmo_heap* H, uint32_t cls, hipStream_t s, int* rc) {
+bool build_block_list(smmo_heap* H, uint32_t cls, hipStream_t s, int* rc) {
     *rc = SMMO_OK;
     if (H->hdr.nlevels < 2 || H->hdr.level_words[0] < SMMO_LIST_MIN_WORDS || (H->dev.tune & SMMO_TUNE_FLAT_ENUM))
         return false;
     unsigned long long* cnt = scratch_counter(H, 3);
     k_fill_u64<<<1, 64, 0, s>>>(cnt, 1, 0);
     if (hipGetLastError() != hipSuccess) { *rc = fail(SMMO_EHIP, "k_fill_u64 launch"); return false; }
-    k_enum_words<<<grid_for(H->hdr.level_words[1], 256), 256, 0, s>>>(H->dev, bm_allocated(cls), scratch_words(H), cnt);
-    if (hipGetLastError() != hipSuccess) { *rc = fail(SMMO_EHIP, "k_enum_words launch"); return false; }
+    k_enum_blocks<<<grid_for(H->hdr.level_words[1], 4), 256, 0, s>>>(H->dev, bm_allocated(cls), scratch_R(H), cnt);
+    if (hipGetLastError() != hipSuccess) { *rc = fail(SMMO_EHIP, "k_enum_blocks launch"); return false; }
     return true;
 }
 
-// grid for the list-form passes: at most one wave per L0 word, at most 32
-// waves per CU, grid-stride beyond
+// grid of the list-form thread-per-block passes: at most 32 waves per CU,
+// grid-stride beyond
 unsigned list_grid(const smmo_heap* H) {
-    const uint64_t waves = std::min<uint64_t>(H->hdr.level_words[0], 256ull * 32);
-    return (unsigned)((waves + 3) / 4);
+    const uint64_t threads = std::min<uint64_t>(H->hdr.num_blocks, 256ull * 32 * 64);
+    return grid_for(threads, 256);
 }
 
 int check_heap_cls(const smmo_heap* H, uint32_t cls) {
@@ -252,17 +262,29 @@ void doall_geometry(const smmo_heap* H, uint32_t& s_log2, uint64_t& nunits, unsi
     grid = (unsigned)((waves + 3) / 4);
 }
 
-template <class M>
-int launch_doall(smmo_heap* H, uint32_t cls, const void* args, uint64_t bytes, hipStream_t s) {
-    typename M::Args a;
-    int rc = unpack_args(a, args, bytes, "parallel_do");
+// `cls` and its subclasses, transitively, in ascending id (a superclass has
+// a smaller id than its subclasses)
+uint32_t subtree(const smmo_heap* H, uint32_t cls, uint32_t* out) {
+    bool in[SMMO_MAX_CLASSES] = {};
+    uint32_t n = 0;
+    for (uint32_t t = cls; t < H->hdr.ncls; ++t) {
+        const uint32_t sup = H->hdr.superclass[t];
+        in[t] = t == cls || (sup && in[sup - 1]);
+        if (in[t]) out[n++] = t;
+    }
+    return n;
+}
+
+// One do-all kernel on one class; with snap_here, the class's snapshot first.
+template <class M, bool kSnap>
+int launch_doall_one(smmo_heap* H, uint32_t cls, const typename M::Args& a, bool snap_here, hipStream_t s) {
+    int rc = SMMO_OK;
+    const bool list = build_block_list(H, cls, s, &rc);
     if (rc) return rc;
-    const bool list = build_word_list(H, cls, s, &rc);
-    if (rc) return rc;
-    const uint32_t* words = list ? scratch_words(H) : nullptr;
-    const unsigned long long* nwords = list ? scratch_counter(H, 3) : nullptr;
-    if (M::kSnapshot) {
-        if (list) k_snapshot<<<list_grid(H), 256, 0, s>>>(H->dev, cls, words, nwords);
+    const uint32_t* R = list ? scratch_R(H) : nullptr;
+    const unsigned long long* nR = list ? scratch_counter(H, 3) : nullptr;
+    if (snap_here) {
+        if (list) k_snapshot<<<list_grid(H), 256, 0, s>>>(H->dev, cls, R, nR);
         else k_snapshot<<<grid_for(H->hdr.num_blocks, 256), 256, 0, s>>>(H->dev, cls, nullptr, nullptr);
         LAUNCH_CHECK("k_snapshot");
     }
@@ -271,14 +293,42 @@ int launch_doall(smmo_heap* H, uint32_t cls, const void* args, uint64_t bytes, h
     unsigned grid;
     doall_geometry(H, s_log2, nunits, grid);
     if (list) {
-        // the list length is known on the device only: units of 16 blocks
-        // keep a sparse class spread over many waves
-        s_log2 = 2;
+        // the list length is known on the device only: the kernel sizes its
+        // runs to at most 16,384 of them; the grid covers that many waves or
+        // one per listed block, whichever is less, at most 32 waves per CU
         nunits = 0;
-        grid = (unsigned)((std::min<uint64_t>(H->hdr.level_words[0] << 2, 256ull * 32) + 3) / 4);
+        grid = (unsigned)((std::min<uint64_t>(std::min<uint64_t>(H->hdr.num_blocks, 16384), 256ull * 32) + 3) / 4);
     }
-    k_doall<M><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, words, nwords, a);
+    k_doall<M, kSnap><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, R, nR, a);
     LAUNCH_CHECK("k_doall");
+    return SMMO_OK;
+}
+
+int snapshot_class(smmo_heap* H, uint32_t cls, hipStream_t s) {
+    int rc = SMMO_OK;
+    const bool list = build_block_list(H, cls, s, &rc);
+    if (rc) return rc;
+    if (list) k_snapshot<<<list_grid(H), 256, 0, s>>>(H->dev, cls, scratch_R(H), scratch_counter(H, 3));
+    else k_snapshot<<<grid_for(H->hdr.num_blocks, 256), 256, 0, s>>>(H->dev, cls, nullptr, nullptr);
+    LAUNCH_CHECK("k_snapshot");
+    return SMMO_OK;
+}
+
+template <class M>
+int launch_doall(smmo_heap* H, uint32_t cls, const void* args, uint64_t bytes, hipStream_t s) {
+    typename M::Args a;
+    int rc = unpack_args(a, args, bytes, "parallel_do");
+    if (rc) return rc;
+    uint32_t cl[SMMO_MAX_CLASSES];
+    const uint32_t n = subtree(H, cls, cl);
+    if (n == 1) return launch_doall_one<M, M::kSnapshot>(H, cls, a, M::kSnapshot, s);
+    // class and subclasses (Sec. 2.1): one kernel per class, every class's
+    // iteration words taken before the first, so no kernel visits objects an
+    // earlier one created
+    for (uint32_t i = 0; i < n; ++i)
+        if ((rc = snapshot_class(H, cl[i], s))) return rc;
+    for (uint32_t i = 0; i < n; ++i)
+        if ((rc = launch_doall_one<M, true>(H, cl[i], a, false, s))) return rc;
     return SMMO_OK;
 }
 
@@ -299,6 +349,8 @@ int launch_nbody(smmo_heap* H, uint32_t cls, uint32_t method, const void* args, 
     smmo_nbody_args a;
     int rc = unpack_args(a, args, bytes, "n-body");
     if (rc) return rc;
+    uint32_t cl[SMMO_MAX_CLASSES];
+    if (subtree(H, cls, cl) != 1) return fail(SMMO_EINVAL, "n-body methods take a class without subclasses");
     rc = check_nbody(H, cls, a);
     if (rc) return rc;
     switch (method) {
@@ -489,11 +541,16 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
             if (a.fx >= heap->hdr.nfields[cls] || a.fy >= heap->hdr.nfields[cls] ||
                 heap->hdr.field_bytes[cls][a.fx] != 4 || heap->hdr.field_bytes[cls][a.fy] != 4)
                 return fail(SMMO_EINVAL, "axpy: fields must be 4-byte fields of the class");
+            // creates and destroys nothing: one streaming kernel per class
+            uint32_t cl[SMMO_MAX_CLASSES];
+            const uint32_t n = subtree(heap, cls, cl);
             const uint64_t nwords = heap->hdr.level_words[0];
             const uint64_t waves = std::min<uint64_t>(nwords, 256ull * SMMO_SWEEP_WAVES_PER_CU);
-            k_doall_axpy<SMMO_SWEEP_GROUPS><<<(unsigned)((waves + 3) / 4), kBlockThreads, 0, s>>>(heap->dev, cls,
-                                                                                                nwords, a);
-            LAUNCH_CHECK("k_doall_axpy");
+            for (uint32_t i = 0; i < n; ++i) {
+                k_doall_axpy<SMMO_SWEEP_GROUPS><<<(unsigned)((waves + 3) / 4), kBlockThreads, 0, s>>>(
+                    heap->dev, cl[i], nwords, a);
+                LAUNCH_CHECK("k_doall_axpy");
+            }
             return SMMO_OK;
         }
         case SMMO_M_DESTROY_ALL: return launch_doall<MDestroyAll>(heap, cls, nullptr, 0, s);
@@ -512,9 +569,13 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
             smmo_stress_args a;
             rc = unpack_args(a, args, args_bytes, "stress");
             if (rc) return rc;
-            if (a.cls_a >= heap->hdr.ncls || a.cls_b >= heap->hdr.ncls || a.cls_a == cls || a.cls_b == cls ||
-                heap->hdr.field_bytes[a.cls_a][0] != 4 || heap->hdr.field_bytes[a.cls_b][0] != 4 || a.lanes > 64)
-                return fail(SMMO_EINVAL, "stress: two other classes with an int32 field 0, lanes <= 64");
+            uint32_t cl[SMMO_MAX_CLASSES];
+            const uint32_t n = subtree(heap, cls, cl);
+            bool other = a.cls_a < heap->hdr.ncls && a.cls_b < heap->hdr.ncls;
+            for (uint32_t i = 0; i < n; ++i) other = other && a.cls_a != cl[i] && a.cls_b != cl[i];
+            if (!other || heap->hdr.field_bytes[a.cls_a][0] != 4 || heap->hdr.field_bytes[a.cls_b][0] != 4 ||
+                a.lanes > 64)
+                return fail(SMMO_EINVAL, "stress: two classes outside the do-all's with an int32 field 0, lanes <= 64");
             return launch_doall<MStress>(heap, cls, args, args_bytes, s);
         }
         case SMMO_M_LIFE_PLAN: return launch_doall<MLifePlan>(heap, cls, args, args_bytes, s);
@@ -542,10 +603,10 @@ int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream) 
     unsigned long long* c = scratch_counter(heap, 1);
     k_fill_u64<<<1, 64, 0, s>>>(c, 1, 0);
     LAUNCH_CHECK("k_fill_u64");
-    const bool list = build_word_list(heap, cls, s, &rc);
+    const bool list = build_block_list(heap, cls, s, &rc);
     if (rc) return rc;
     if (list)
-        k_live_count<<<list_grid(heap), 256, 0, s>>>(heap->dev, cls, scratch_words(heap), scratch_counter(heap, 3), c);
+        k_live_count<<<list_grid(heap), 256, 0, s>>>(heap->dev, cls, scratch_R(heap), scratch_counter(heap, 3), c);
     else
         k_live_count<<<grid_for(heap->hdr.num_blocks, 256), 256, 0, s>>>(heap->dev, cls, nullptr, nullptr, c);
     LAUNCH_CHECK("k_live_count");

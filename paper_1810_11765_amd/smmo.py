@@ -44,12 +44,14 @@ TUNE_NO_COALESCE = 2
 TUNE_STATS = 4
 TUNE_FORCE_FAIL = 8
 TUNE_FLAT_ENUM = 32
+TUNE_FREE_SPREAD = 64
 COUNTERS = ["alloc_obj", "free_obj", "block_init", "block_free", "inval_rollback", "type_rollback",
-            "find_fail", "reserve_fail", "spin", "reserve_atomic"]
+            "find_fail", "reserve_fail", "spin", "reserve_atomic", "guard_alloc", "guard_spin", "guard_inval",
+            "oom"]
 
 
 class ClassDesc(C.Structure):
-    _fields_ = [("nfields", C.c_uint32), ("field_bytes", C.POINTER(C.c_uint8))]
+    _fields_ = [("nfields", C.c_uint32), ("field_bytes", C.POINTER(C.c_uint8)), ("superclass", C.c_uint32)]
 
 
 class Layout(C.Structure):
@@ -153,12 +155,31 @@ def check(rc: int) -> None:
         raise SmmoError(f"{L.smmo_strerror(rc).decode()} ({rc}): {L.smmo_last_error().decode()}")
 
 
+def class_spec(c):
+    """(own field sizes, superclass id or None) of a class given either as a
+    list of field byte sizes or as {"fields": [...], "super": id}."""
+    if isinstance(c, dict):
+        return list(c.get("fields", [])), c.get("super")
+    return list(c), None
+
+
+def full_fields(classes):
+    """Every class's field sizes, inherited fields first."""
+    out = []
+    for c in classes:
+        own, sup = class_spec(c)
+        out.append((list(out[sup]) if sup is not None else []) + own)
+    return out
+
+
 def _descs(classes):
-    arrs = [(C.c_uint8 * len(c))(*c) for c in classes]
+    specs = [class_spec(c) for c in classes]
+    arrs = [(C.c_uint8 * max(len(own), 1))(*own) for own, _ in specs]
     descs = (ClassDesc * len(classes))()
-    for d, a, c in zip(descs, arrs, classes):
-        d.nfields = len(c)
+    for d, a, (own, sup) in zip(descs, arrs, specs):
+        d.nfields = len(own)
         d.field_bytes = C.cast(a, C.POINTER(C.c_uint8))
+        d.superclass = 0 if sup is None else sup + 1
     return descs, arrs
 
 
@@ -190,14 +211,17 @@ def _blob(args):
 
 
 class Heap:
-    """A heap of `num_blocks` blocks for `classes` (lists of field byte sizes)
-    inside one torch uint8 device tensor owned by this object."""
+    """A heap of `num_blocks` blocks for `classes` (lists of field byte sizes,
+    or {"fields": [...], "super": id} for a subclass) inside one torch uint8
+    device tensor owned by this object.  `classes` holds every class's full
+    field list afterwards, inherited fields first."""
 
     def __init__(self, classes, num_blocks: int, device="cuda", stream=None, dev_ptr: int | None = None):
         import torch
-        self.classes = [list(c) for c in classes]
+        self.specs = list(classes)
+        self.classes = full_fields(self.specs)
         self.num_blocks = num_blocks
-        nbytes = heap_bytes(self.classes, num_blocks)
+        nbytes = heap_bytes(self.specs, num_blocks)
         if dev_ptr is None:
             # 4 KiB slack so the buffer can be aligned to 256 bytes
             self.buf = torch.empty(nbytes + 4096, dtype=torch.uint8, device=device)
@@ -207,7 +231,7 @@ class Heap:
             self.buf = None                      # memory owned by the caller (an arena range)
             self.base = dev_ptr
         self.nbytes = nbytes
-        descs, _keep = _descs(self.classes)
+        descs, _keep = _descs(self.specs)
         h = C.c_void_p()
         check(lib().smmo_heap_create(descs, len(self.classes), num_blocks, C.c_void_p(self.base), nbytes,
                                      _stream(stream), C.byref(h)))

@@ -53,6 +53,34 @@ def test_layout_matches_capacity_formula(classes):
         assert list(lay.field_bytes[: len(offs)]) == classes[t]
 
 
+def test_layout_with_subclasses_by_hand():
+    """Base {i32, i32}; Sub: Base + {f64}; Leaf: Sub + nothing; Tiny {i8, i8}.
+    Sizes 8, 16, 16, 2: capacities 64*2 // size = 16, 8, 8, 64; SOA arrays of
+    the inherited fields first, each 128-B aligned."""
+    specs = [([4, 4], None), ([8], 0), ([], 1), ([1, 1], None)]
+    full = layout_ref.flatten(specs)
+    assert full == [[4, 4], [4, 4, 8], [4, 4, 8], [1, 1]]
+    block, per = layout_ref.layout(full)
+    assert per == [(16, [0, 128]), (8, [0, 128, 256]), (8, [0, 128, 256]), (64, [0, 128])]
+    assert block == 384
+    classes = [{"fields": own, "super": sup} if sup is not None else own for own, sup in specs]
+    for t, (n, offs) in enumerate(per):
+        lay = S.layout_of(classes, t)
+        assert lay.capacity == n and lay.block_bytes == block
+        assert list(lay.field_offset[: len(offs)]) == offs
+        assert list(lay.field_bytes[: lay.nfields]) == full[t]
+    assert S.full_fields(classes) == full
+
+
+def test_layout_rejects_bad_subclasses():
+    for bad in ([[4], {"fields": [4], "super": 1}],                  # superclass not a smaller id
+                [[4], {"fields": [4], "super": 5}],
+                [[4] * 10, {"fields": [4] * 7, "super": 0}],        # 17 fields in all
+                [{"fields": [], "super": None}]):                   # no field at all
+        with pytest.raises(S.SmmoError):
+            S.layout_of(bad, len(bad) - 1)
+
+
 def test_layout_rejects_bad_classes():
     for bad in ([[1], [8] * 9], [[3]], [[]], [[4]] * 17):
         with pytest.raises(S.SmmoError):
@@ -73,11 +101,11 @@ def test_heap_bytes_and_header_struct_offsets(tmp_path):
                 "int main(){P(magic)P(num_blocks)P(ncls)P(block_bytes)P(nlevels)P(level_words)P(level_off)"
                 "P(bitmap_words)P(off_status)P(off_type)P(off_alloc)P(off_iter)P(off_bitmaps)P(off_scratch)"
                 "P(scratch_bytes)P(off_data)P(total_bytes)P(capacity)P(nfields)P(field_bytes)P(field_off)"
-                "P(tune_flags)P(lookups)P(force_fail_ppm)return 0;}\n")
+                "P(tune_flags)P(lookups)P(force_fail_ppm)P(superclass)return 0;}\n")
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", prog], check=True)
     got = [int(v) for v in subprocess.run([prog], capture_output=True, text=True).stdout.split()]
     assert got == [0, 16, 24, 32, 40, 48, 96, 144, 152, 160, 168, 176, 184, 192, 200, 208, 216, 224, 352, 480,
-                   1504, 2528, 2532, 2536]
+                   1504, 2528, 2532, 2536, 2544]
     assert heapcheck.MAGIC == 0x504145484F4D4D53
 
 
