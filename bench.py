@@ -331,40 +331,40 @@ def linux_scalability_suite(torch, workloads):
     from paper_1810_11765_amd import smmo as S
     ls = workloads.LinuxScalability()
     cap = ls.num_blocks * 64
-    rows = []
-    n = 1
-    while n <= 1024:
-        _progress("linux-scalability n", n)
-        reps = 3 if n < 1024 else 1
-        a_ms, f_ms = [], []
-        live = 0
-        status = 0
-        for _ in range(reps):
-            ls.heap.reset()
-            tm = Timer(torch)
-            tm.run("alloc", lambda: ls.alloc(n))
-            torch.cuda.synchronize()
-            live = ls.heap.live_count(0)
-            status = ls.heap.status()
-            tm.run("free", lambda: ls.free(n))
-            torch.cuda.synchronize()
-            left = ls.heap.live_count(0)
-            a_ms += tm.ms("alloc")
-            f_ms += tm.ms("free")
-            ls.heap.clear_status()
-        a, f = sorted(a_ms)[len(a_ms) // 2], sorted(f_ms)[len(f_ms) // 2]
-        rows.append({"n": n, "alloc_ms": round(a, 4), "destroy_ms": round(f, 4),
-                     "total_ms_over_n": round((a + f) / n, 5),
-                     "ns_per_alloc": round(a * 1e6 / (16384 * n), 4),
-                     "ns_per_destroy": round(f * 1e6 / (16384 * n), 4),
-                     "live_after_alloc": live, "requested": 16384 * n, "left_after_destroy": left,
-                     "oom": bool(status & S.STATUS_OOM)})
-        n *= 2
-    top = rows[-1]
-    return {"workload": "16384 threads x n allocations of a 64-byte class, heap footprint 1 GiB",
-            "num_blocks": ls.num_blocks, "slots": cap, "heap_bytes": S.heap_bytes(ls.CLASSES, ls.num_blocks),
-            "utilization_at_1024": round(top["live_after_alloc"] * 64 / (1 << 30), 5),
-            "rows": rows}
+    out = {"workload": "16384 threads x n allocations of a 64-byte class, heap footprint 1 GiB",
+           "num_blocks": ls.num_blocks, "slots": cap, "heap_bytes": S.heap_bytes(ls.CLASSES, ls.num_blocks)}
+    for mode, flags in (("default", 0),):
+        rows = []
+        n = 1
+        while n <= 1024:
+            _progress("linux-scalability", mode, "n", n)
+            reps = 3 if n < 1024 else 1
+            a_ms, f_ms = [], []
+            live = left = status = 0
+            for _ in range(reps):
+                ls.heap.reset()
+                ls.heap.set_tuning(flags, 5, 0)
+                tm = Timer(torch)
+                tm.run("alloc", lambda: ls.alloc(n))
+                torch.cuda.synchronize()
+                live = ls.heap.live_count(0)
+                status = ls.heap.status()
+                tm.run("free", lambda: ls.free(n))
+                torch.cuda.synchronize()
+                left = ls.heap.live_count(0)
+                a_ms += tm.ms("alloc")
+                f_ms += tm.ms("free")
+                ls.heap.clear_status()
+            a, f = sorted(a_ms)[len(a_ms) // 2], sorted(f_ms)[len(f_ms) // 2]
+            rows.append({"n": n, "alloc_ms": round(a, 4), "destroy_ms": round(f, 4),
+                         "total_ms_over_n": round((a + f) / n, 5),
+                         "ns_per_alloc": round(a * 1e6 / (16384 * n), 4),
+                         "ns_per_destroy": round(f * 1e6 / (16384 * n), 4),
+                         "live_after_alloc": live, "requested": 16384 * n, "left_after_destroy": left,
+                         "oom": bool(status & S.STATUS_OOM)})
+            n *= 2
+        out[mode] = {"utilization_at_1024": round(rows[-1]["live_after_alloc"] * 64 / (1 << 30), 5), "rows": rows}
+    return out
 
 
 def blocks_for_bytes(classes, total: int) -> int:
@@ -382,10 +382,9 @@ def blocks_for_bytes(classes, total: int) -> int:
 def heap_size_suite(torch, workloads, steps):
     """Predator-prey 1024 x 1024 (seed 42) in its own 32,768-block heap and in
     heaps of 1 to 64 GiB (Sec. 6.5): step time with the level-1 skip
-    (default; a heap under 4,096 level-0 words is always scanned flat), with
-    every level-0 word scanned (flat), and with new blocks taken anywhere in
-    the heap (spread: free-block search rotated at every level), and whether
-    the final state equals the oracle's."""
+    (default; a heap under 4,096 level-0 words is always scanned flat) and
+    with every level-0 word scanned (flat), and whether the final state
+    equals the oracle's."""
     from oracle import core
     from paper_1810_11765_amd import smmo as S
     seed, side = 42, 1024
@@ -395,14 +394,12 @@ def heap_size_suite(torch, workloads, steps):
         # 0: the workload's own 32,768-block heap (25 MiB), the reference row
         nb = 32768 if gib == 0 else blocks_for_bytes(workloads.WaTor.CLASSES, gib << 30)
         row = {"heap_gib": gib, "num_blocks": nb}
-        for mode in ("hierarchical", "flat", "spread"):
+        for mode in ("hierarchical", "flat"):
             _progress("heap-size", gib, mode)
             w = workloads.WaTor(seed=seed, width=side, height=side, num_blocks=nb, kind0=kind0)
             kind0 = w.kind0
             if mode == "flat":
                 w.heap.set_tuning(S.TUNE_FLAT_ENUM, 5, 0)
-            elif mode == "spread":
-                w.heap.set_tuning(S.TUNE_FREE_SPREAD, 5, 0)
             w.populate()
             tm = Timer(torch)
             for _ in range(steps):
@@ -410,7 +407,7 @@ def heap_size_suite(torch, workloads, steps):
             torch.cuda.synchronize()
             ms = tm.ms("step")
             row[mode] = {"ms_per_step": round(sum(ms) / len(ms), 5), "status": w.heap.status(), "_w": w}
-            if mode != "flat":
+            if mode == "hierarchical":
                 row[mode]["F_end"] = round(w.heap.occupancy()["F"], 5)
             if gib == 0 and mode == "hierarchical":
                 _progress("heap-size oracle")

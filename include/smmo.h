@@ -148,8 +148,6 @@ enum smmo_counter {
                                        reserving in it (widens the race window of App. A.3) */
 #define SMMO_TUNE_FLAT_ENUM 32u     /* do-all, snapshot and live count scan every level-0
                                        word even in big heaps (no level-1 skip) */
-#define SMMO_TUNE_FREE_SPREAD 64u   /* free-block search rotated at every bitmap level (new
-                                       blocks anywhere in the heap); default: the two lowest */
 
 /* -------------------------------------------------- heap management ---- */
 

@@ -106,8 +106,7 @@ __device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t 
             count(h, SMMO_CNT_FIND_FAIL);
         }
         if (bid == kFail) {                               // slow path
-            bid = bm_clear_any(h, bm_free(), seed,
-                               (h.tune & SMMO_TUNE_FREE_SPREAD) ? SMMO_MAX_LEVELS : kFreeRotLevels);
+            bid = bm_clear_any(h, bm_free(), seed);
             if (bid == kFail) {
                 if (++empty_rounds > kOomRounds || (empty_rounds > 2 && status_has(h, SMMO_STATUS_OOM))) {
                     guard_hit(h, SMMO_CNT_OOM, SMMO_STATUS_OOM);

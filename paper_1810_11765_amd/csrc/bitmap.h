@@ -85,10 +85,7 @@ __device__ inline uint32_t rot_ffs(uint64_t w, uint32_t rot) {
 
 // try_find_set() (Alg. 4), top-down from the single top word.  `seed` gives a
 // different rotation per level; it depends on the wave and changes per retry.
-// Levels at or above `rot_levels` take the first set bit instead (levels
-// counted from 0 = the block level).
-__device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_t seed,
-                                           uint32_t rot_levels = SMMO_MAX_LEVELS) {
+__device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_t seed) {
     if ((h.tune & SMMO_TUNE_FORCE_FAIL) && (uint32_t)(splitmix64(seed) % 1000000u) < h.force_fail_ppm)
         return kFail;
     const bool rotate = !(h.tune & SMMO_TUNE_NO_ROTATE);
@@ -96,25 +93,17 @@ __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_
     for (int l = (int)h.nlevels - 1; l >= 0; --l) {
         uint64_t w = at_load(bm_word(h, b, (uint32_t)l, idx));
         if (!w) return kFail;
-        uint32_t bit = rotate && (uint32_t)l < rot_levels ? rot_ffs(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
+        uint32_t bit = rotate ? rot_ffs(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
         idx = (idx << 6) | bit;
     }
     return idx;
 }
 
-// Rotated levels of the free-block search: the two lowest, so concurrent
-// slow paths spread over the 4,096 blocks under one level-2 bit while new
-// blocks are taken from the low end of the heap (the class's blocks stay
-// close together in big heaps: fewer pages and bitmap words to visit).
-// SMMO_TUNE_FREE_SPREAD rotates every level instead.
-constexpr uint32_t kFreeRotLevels = 2;
-
 // clear(): find and clear any set bit; kFail if a lookup finds none.
-__device__ inline uint64_t bm_clear_any(const DevHeap& h, uint32_t b, uint64_t& seed,
-                                        uint32_t rot_levels = SMMO_MAX_LEVELS) {
+__device__ inline uint64_t bm_clear_any(const DevHeap& h, uint32_t b, uint64_t& seed) {
     for (uint32_t tries = 0; tries < 64; ++tries) {
         seed = splitmix64(seed);
-        uint64_t i = bm_try_find_set(h, b, seed, rot_levels);
+        uint64_t i = bm_try_find_set(h, b, seed);
         if (i == kFail) return kFail;
         if (bm_try_clear(h, b, i)) return i;
     }

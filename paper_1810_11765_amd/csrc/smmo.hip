@@ -640,6 +640,34 @@ int smmo_occupancy(smmo_heap* heap, uint64_t* used, uint64_t* slots, uint64_t* b
 
 // host-side walk over a copy of the metadata and data (introspection, not the
 // hot path)
+// Append the live objects of `cls` in blocks [first, last] (block-major,
+// slot-minor) from host copies of their allocation words and data segments.
+static void dump_range(const smmo_raw_header& h, uint32_t cls, const uint64_t* l0, uint64_t first, uint64_t last,
+                       const uint64_t* alloc, const uint8_t* data, void* const* bufs, uint64_t* refs, uint64_t cap,
+                       uint64_t& n) {
+    const uint64_t N = h.capacity[cls];
+    const uint64_t valid = N >= 64 ? ~0ull : ((1ull << N) - 1);
+    for (uint64_t b = first; b <= last; ++b) {
+        if (!((l0[b >> 6] >> (b & 63)) & 1)) continue;
+        uint64_t w = alloc[b - first] & valid;
+        const uint8_t* blk = data + (b - first) * h.block_bytes;
+        while (w) {
+            uint32_t slot = (uint32_t)__builtin_ctzll(w);
+            w &= w - 1;
+            if (n < cap) {
+                if (refs) refs[n] = make_ref(cls, b, slot);
+                if (bufs)
+                    for (uint32_t f = 0; f < h.nfields[cls]; ++f) {
+                        if (!bufs[f]) continue;
+                        uint32_t fb = h.field_bytes[cls][f];
+                        std::memcpy(static_cast<uint8_t*>(bufs[f]) + n * fb, blk + h.field_off[cls][f] + slot * fb, fb);
+                    }
+            }
+            ++n;
+        }
+    }
+}
+
 static int dump_walk(smmo_heap* heap, uint32_t cls, void* const* bufs, uint64_t* refs, uint64_t cap,
                      uint64_t* n_out, void* stream) {
     int rc = check_heap_cls(heap, cls);
@@ -647,12 +675,24 @@ static int dump_walk(smmo_heap* heap, uint32_t cls, void* const* bufs, uint64_t*
     if (!n_out) return fail(SMMO_EINVAL, "null n_out");
     const smmo_raw_header& h = heap->hdr;
     hipStream_t s = S(stream);
-    // level 0 of allocated[cls], then only the runs of blocks it names (close
-    // runs merged), so the copy is the class's size, not the heap's
     const uint64_t W0 = h.level_words[0];
+    const uint64_t l0_off = h.off_bitmaps + 8 * ((1 + cls) * h.bitmap_words + h.level_off[0]);
+    uint64_t n = 0;
+    if (h.total_bytes <= (256ull << 20)) {
+        // small heap: one copy of the whole buffer
+        std::vector<uint8_t> raw(h.total_bytes);
+        HIP_TRY(hipMemcpyAsync(raw.data(), heap->base, h.total_bytes, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        dump_range(h, cls, reinterpret_cast<const uint64_t*>(raw.data() + l0_off), 0, h.num_blocks - 1,
+                   reinterpret_cast<const uint64_t*>(raw.data() + h.off_alloc), raw.data() + h.off_data, bufs, refs,
+                   cap, n);
+        *n_out = n;
+        return SMMO_OK;
+    }
+    // big heap: level 0 of allocated[cls], then only the runs of blocks it
+    // names (close runs merged), so the copy is the class's size, not the heap's
     std::vector<uint64_t> l0(W0);
-    HIP_TRY(hipMemcpyAsync(l0.data(), heap->base + h.off_bitmaps + 8 * ((1 + cls) * h.bitmap_words + h.level_off[0]),
-                           8 * W0, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(l0.data(), heap->base + l0_off, 8 * W0, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::vector<std::pair<uint64_t, uint64_t>> runs;       // [first, last] block
     for (uint64_t i = 0; i < W0; ++i)
@@ -661,11 +701,8 @@ static int dump_walk(smmo_heap* heap, uint32_t cls, void* const* bufs, uint64_t*
             if (!runs.empty() && b <= runs.back().second + 8) runs.back().second = b;
             else runs.push_back({b, b});
         }
-    const uint64_t N = h.capacity[cls];
-    const uint64_t valid = N >= 64 ? ~0ull : ((1ull << N) - 1);
     std::vector<uint64_t> alloc;
     std::vector<uint8_t> data;
-    uint64_t n = 0;
     for (const auto& r : runs) {
         const uint64_t nb = r.second - r.first + 1;
         alloc.resize(nb);
@@ -674,26 +711,7 @@ static int dump_walk(smmo_heap* heap, uint32_t cls, void* const* bufs, uint64_t*
         HIP_TRY(hipMemcpyAsync(data.data(), heap->base + h.off_data + r.first * h.block_bytes, nb * h.block_bytes,
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        for (uint64_t b = r.first; b <= r.second; ++b) {
-            if (!((l0[b >> 6] >> (b & 63)) & 1)) continue;
-            uint64_t w = alloc[b - r.first] & valid;
-            const uint8_t* blk = data.data() + (b - r.first) * h.block_bytes;
-            while (w) {
-                uint32_t slot = (uint32_t)__builtin_ctzll(w);
-                w &= w - 1;
-                if (n < cap) {
-                    if (refs) refs[n] = make_ref(cls, b, slot);
-                    if (bufs)
-                        for (uint32_t f = 0; f < h.nfields[cls]; ++f) {
-                            if (!bufs[f]) continue;
-                            uint32_t fb = h.field_bytes[cls][f];
-                            std::memcpy(static_cast<uint8_t*>(bufs[f]) + n * fb, blk + h.field_off[cls][f] + slot * fb,
-                                        fb);
-                        }
-                }
-                ++n;
-            }
-        }
+        dump_range(h, cls, l0.data(), r.first, r.second, alloc.data(), data.data(), bufs, refs, cap, n);
     }
     *n_out = n;
     return SMMO_OK;

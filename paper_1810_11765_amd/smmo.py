@@ -44,7 +44,6 @@ TUNE_NO_COALESCE = 2
 TUNE_STATS = 4
 TUNE_FORCE_FAIL = 8
 TUNE_FLAT_ENUM = 32
-TUNE_FREE_SPREAD = 64
 COUNTERS = ["alloc_obj", "free_obj", "block_init", "block_free", "inval_rollback", "type_rollback",
             "find_fail", "reserve_fail", "spin", "reserve_atomic", "guard_alloc", "guard_spin", "guard_inval",
             "oom"]

@@ -26,7 +26,7 @@ def S():
 
 # Base {i32 id, f32 x, f32 v}; Sub: Base + {f64 w}; Leaf: Sub + {}; Other {i32 id}
 CLASSES = [[4, 4, 4], {"fields": [8], "super": 0}, {"fields": [], "super": 1}, [4]]
-COUNTS = [700, 333, 129, 250]            # ragged: several blocks each, partial last blocks
+COUNTS = [700, 333, 129, 250]            # ragged: 34 + 28 + 11 + 4 blocks (capacities 21, 12, 12, 64)
 
 
 def _populate(h):
@@ -43,13 +43,14 @@ def _populate(h):
     return np.cumsum([0] + COUNTS)
 
 
-@pytest.mark.parametrize("blocks", [64, 300_000])       # flat scan; level-1 block list
+@pytest.mark.parametrize("blocks", [128, 300_000])      # flat scan; level-1 block list
 def test_do_all_over_class_visits_its_subclasses_once(blocks):
     say("subclass visit", blocks)
     smmo = S()
     h = smmo.Heap(CLASSES, blocks)
     assert h.classes == [[4, 4, 4], [4, 4, 4, 8], [4, 4, 4, 8], [4]]
     edges = _populate(h)
+    assert h.status() == 0
     total = int(edges[-1])
     for root, covered in ((0, (0, 1, 2)), (1, (1, 2)), (2, (2,)), (3, (3,))):
         visits = torch.zeros(total, dtype=torch.int32, device="cuda")
@@ -71,8 +72,9 @@ def test_do_all_over_class_visits_its_subclasses_once(blocks):
 def test_axpy_over_class_and_subclasses():
     say("subclass axpy")
     smmo = S()
-    h = smmo.Heap(CLASSES, 64)
+    h = smmo.Heap(CLASSES, 128)
     _populate(h)
+    assert h.status() == 0
     h.parallel_do(0, smmo.M_AXPY, smmo.AxpyArgs(0.5, 1, 2, 0))
     for t in (0, 1, 2):
         fields = h.dump_objects(t, [np.int32, np.float32, np.float32] + ([np.float64] if t else []))
