@@ -37,9 +37,21 @@ struct MAxpy {
 // SOA segment per 16 lanes).  A wave owns a unit of one L0 word of
 // allocated[T]; it fetches the unit's 64 allocation words with one coalesced
 // load and walks the word's set bits eight blocks at a time, so eight blocks'
-// loads are in flight before the first store.  A dead slot keeps its bytes
-// (the old value is stored back), which is safe because nothing else writes
-// this class's slots during the do-all.
+// loads are in flight before the first store.  Field loads and stores are
+// non-temporal: every byte is touched once, and streaming them past the
+// caches measured about 5% more bandwidth on MI355X.  A dead slot keeps its
+// bytes (the old value is stored back), which is safe because nothing else
+// writes this class's slots during the do-all.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ inline float4 load_stream(const float4* p) {
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline void store_stream(float4* p, const float4& v) {
+    const f32x4 r = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(r, reinterpret_cast<f32x4*>(p));
+}
+
 template <int kGroups>
 __global__ __launch_bounds__(kBlockThreads) void k_doall_axpy(DevHeap h, uint32_t cls, uint64_t nwords,
                                                                smmo_axpy_args a) {
@@ -72,8 +84,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall_axpy(DevHeap h, uint32_
                 uint8_t* blk = h.data + ((w << 6) | b) * h.block_bytes;
                 py[u] = reinterpret_cast<float4*>(blk + oy) + q;
                 if (live4[u]) {
-                    xv[u] = reinterpret_cast<const float4*>(blk + ox)[q];
-                    yv[u] = *py[u];
+                    xv[u] = load_stream(reinterpret_cast<const float4*>(blk + ox) + q);
+                    yv[u] = load_stream(py[u]);
                 }
             }
 #pragma unroll
@@ -85,7 +97,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall_axpy(DevHeap h, uint32_
                 if (m & 2) r.y = yv[u].y + a.a * xv[u].y;
                 if (m & 4) r.z = yv[u].z + a.a * xv[u].z;
                 if (m & 8) r.w = yv[u].w + a.a * xv[u].w;
-                *py[u] = r;
+                store_stream(py[u], r);
             }
         }
     }

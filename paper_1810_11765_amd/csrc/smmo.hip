@@ -18,13 +18,15 @@
 
 using namespace smmo;
 
-// Launch shape of the streaming sweep: waves per CU (256 CUs) and groups of
-// four blocks in flight per wave.
+// Launch shape of the streaming sweep: waves per CU (256 CUs; beyond the
+// resident limit, workgroups wait for a slot) and groups of four blocks in
+// flight per wave.  128 x 4 measured best on MI355X with non-temporal field
+// access (one L0 word per wave at 2^21 blocks).
 #ifndef SMMO_SWEEP_WAVES_PER_CU
-#define SMMO_SWEEP_WAVES_PER_CU 32
+#define SMMO_SWEEP_WAVES_PER_CU 128
 #endif
 #ifndef SMMO_SWEEP_GROUPS
-#define SMMO_SWEEP_GROUPS 2
+#define SMMO_SWEEP_GROUPS 4
 #endif
 
 struct smmo_heap {
