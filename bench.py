@@ -268,7 +268,7 @@ def batch_sub(torch, steps=200, count=256):
 
 
 def _progress(*a):
-    print("[suite]", *a, file=sys.stderr, flush=True)
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def _wator_same(w, oracle_state):
@@ -464,6 +464,7 @@ def main():
     if args.suite:
         run_suite(args, torch, workloads)
         return
+    _progress("life-like grid")
     ms_step, per, status, life_extra = life_bench(torch, workloads, args.steps, args.warmup)
     kname, roof = roofline_for(per)
     out = {
@@ -487,9 +488,12 @@ def main():
         "device_status": status,
     }
     if not args.no_sub:
+        _progress("alloc microbench")
         out["alloc_microbench"] = alloc_sub(torch, workloads)
+        _progress("sweep")
         out["sweep"] = sweep_sub(torch, args.sweep_blocks)
         if not args.no_batch:
+            _progress("predator-prey plain vs batched vs served")
             out["predator_prey_plain_vs_batched"] = batch_sub(torch)
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
@@ -499,6 +503,7 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
+        _progress("cpu baseline")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
