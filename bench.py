@@ -193,7 +193,85 @@ def alloc_sub(torch, workloads):
     return {"initial_alloc_mobj_s": round(262144 / (alloc_ms * 1e-3) / 1e6, 2),
             "churn_alloc_destroy_mobj_s": round(churn_objs / (churn_ms * 1e-3) / 1e6, 2),
             "churn_ms_per_round": round(churn_ms / 10, 4), "objects_per_round": churn_objs // 10,
+            "reservation_ors_per_allocated_object": round(st["reserve_atomic"] / st["alloc_obj"], 4),
             "status": wl.heap.status()}
+
+
+def atomic_ceiling(torch):
+    """Reference rates of 64-bit agent-scope atomic ORs on this GPU: every
+    lane on its own word (2^24 words), and a whole wavefront on one word."""
+    from paper_1810_11765_amd import smmo as S
+    words = torch.zeros(1 << 24, dtype=torch.int64, device="cuda")
+    out = {}
+    for name, lpw in (("distinct_words", 1), ("one_word_per_wave", 64)):
+        nthreads, rounds = 1 << 24, 16
+        for _ in range(2):
+            S.atomic_probe(words, lpw, nthreads, rounds)
+        tm = Timer(torch)
+        for _ in range(5):
+            tm.run("p", lambda: S.atomic_probe(words, lpw, nthreads, rounds))
+        torch.cuda.synchronize()
+        ms = sorted(tm.ms("p"))[2]
+        out[name + "_gops_s"] = round(nthreads * rounds / (ms * 1e-3) / 1e9, 2)
+    del words
+    return out
+
+
+def alloc_scaled_sub(torch):
+    """Device allocation at scale: 2^22 threads x 4 allocations of the
+    alloc-microbench class into a 2^18-block heap (16,777,216 objects, every
+    slot), objects untouched; then every object destroys itself (one do-all).
+    Atomics per object from a second run with the device counters on."""
+    from paper_1810_11765_amd import smmo as S
+    res = {}
+    for counted in (False, True):
+        h = S.Heap([[4, 4, 4]], 1 << 18)
+        if counted:
+            h.set_tuning(S.TUNE_STATS, 5, 0)
+        tm = Timer(torch)
+        tm.run("alloc", lambda: h.parallel_alloc(0, 1 << 22, 4, S.CTOR_NONE))
+        torch.cuda.synchronize()
+        live = h.live_count(0)
+        tm.run("destroy", lambda: h.parallel_do(0, S.M_DESTROY_ALL))
+        torch.cuda.synchronize()
+        if counted:
+            st = h.stats()
+            res["reservation_ors_per_object"] = round(st["reserve_atomic"] / max(st["alloc_obj"], 1), 4)
+            res["blocks_initialized"] = st["block_init"]
+        else:
+            a, d = tm.ms("alloc")[0], tm.ms("destroy")[0]
+            res.update({"objects": live, "alloc_ms": round(a, 4), "destroy_ms": round(d, 4),
+                        "alloc_mobj_s": round(live / (a * 1e-3) / 1e6, 1),
+                        "destroy_mobj_s": round(live / (d * 1e-3) / 1e6, 1),
+                        "left_after_destroy": h.live_count(0), "status": h.status()})
+        h.close()
+    return res
+
+
+def nbody_sub(torch, workloads, steps=2):
+    """N-body with merging at 262,144 bodies: per-phase event times of
+    `steps` steps after one warm-up step; interactions/s of the all-pairs
+    force (device_do) and its FP32 rate at 14 flops per interaction (the
+    correctly rounded sqrt and division counted as one flop each) against the
+    157.3 TFLOP/s vector peak."""
+    from paper_1810_11765_amd import smmo as S
+    nb = workloads.NBody(seed=42)
+    nb.populate()
+    nb.step()
+    tm = Timer(torch)
+    for _ in range(steps):
+        tm.run("merge", nb.merge)
+        tm.run("force", lambda: nb.phase(S.M_NBODY_FORCE))
+        tm.run("move", lambda: nb.phase(S.M_NBODY_MOVE))
+    torch.cuda.synchronize()
+    n = nb.heap.live_count(0)
+    f = sum(tm.ms("force")) / steps
+    inter = n * (n - 1)
+    tf = 14.0 * inter / (f * 1e-3) / 1e12
+    return {"bodies_live": n, "ms_per_step": round((sum(tm.ms("merge")) + sum(tm.ms("force")) + sum(tm.ms("move"))) / steps, 3),
+            "force_ms": round(f, 3), "merge_ms": round(sum(tm.ms("merge")) / steps, 3),
+            "interactions_per_s": round(inter / (f * 1e-3), 1), "fp32_tflops_at_14_per_interaction": round(tf, 2),
+            "fp32_vector_peak_frac": round(tf / 157.3, 4), "status": nb.heap.status()}
 
 
 def sweep_sub(torch, nblocks):
@@ -211,6 +289,24 @@ def sweep_sub(torch, nblocks):
     torch.cuda.synchronize()
     ms = sorted(tm.ms("sweep"))[len(tm.ms("sweep")) // 2]
     gbs = 12.0 * n / (ms * 1e-3) / 1e9
+    # about half of the objects destroyed at random (fixed seed): the sweep
+    # still streams whole block segments, so its algorithmic rate (live bytes
+    # only) shows what fragmentation costs
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(42)
+    idx = torch.nonzero(torch.rand(n, device="cuda", generator=gen) < 0.5).flatten()
+    refs = idx | (1 << 56)                     # fresh heap: object i sits in block i/64, slot i%64
+    del idx
+    h.parallel_destroy(refs, refs.numel(), 1)
+    del refs
+    live_half = h.live_count(0)
+    for _ in range(3):
+        h.parallel_do(0, S.M_AXPY, args)
+    tm2 = Timer(torch)
+    for _ in range(20):
+        tm2.run("sweep", lambda: h.parallel_do(0, S.M_AXPY, args))
+    torch.cuda.synchronize()
+    ms_half = sorted(tm2.ms("sweep"))[10]
     status = h.status()
     del h
     # reference: the vendor elementwise kernel on the same access mix (two
@@ -231,7 +327,11 @@ def sweep_sub(torch, nblocks):
             "kernel": "k_doall_axpy<4>", "traffic": measured_traffic("k_doall_axpy<4>@2^21"),
             "plain_array_reference_gbs": round(ref_gbs, 1),
             "fraction_of_plain_array_reference": round(gbs / ref_gbs, 3),
-            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "status": status}
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "half_fill": {"live_objects": live_half, "ms_median": round(ms_half, 4),
+                          "algorithmic_gbs": round(12.0 * live_half / (ms_half * 1e-3) / 1e9, 1),
+                          "field_segment_gbs": round(12.0 * n / (ms_half * 1e-3) / 1e9, 1)},
+            "status": status}
 
 
 def batch_sub(torch, steps=200, count=256):
@@ -490,8 +590,14 @@ def main():
     if not args.no_sub:
         _progress("alloc microbench")
         out["alloc_microbench"] = alloc_sub(torch, workloads)
+        _progress("atomic reference")
+        out["atomic_reference"] = atomic_ceiling(torch)
+        _progress("alloc at scale")
+        out["alloc_scaled"] = alloc_scaled_sub(torch)
         _progress("sweep")
         out["sweep"] = sweep_sub(torch, args.sweep_blocks)
+        _progress("n-body")
+        out["nbody"] = nbody_sub(torch, workloads)
         if not args.no_batch:
             _progress("predator-prey plain vs batched vs served")
             out["predator_prey_plain_vs_batched"] = batch_sub(torch)

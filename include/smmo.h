@@ -447,6 +447,18 @@ int smmo_batch_remaining(smmo_batch* batch, uint32_t* out, void* stream);
 /* Workgroups of the persistent kernel (the occupancy-bounded grid). */
 int smmo_batch_grid(const smmo_batch* batch, uint32_t* workgroups);
 
+/* ------------------------------------------------------- measurement ---- */
+
+/* Atomic-throughput reference for the allocator (not part of the method):
+ * nthreads device threads each perform `rounds` 64-bit atomic ORs (agent
+ * scope, relaxed, value returned and consumed) on words[(t / lanes_per_word)
+ * % nwords] — lanes_per_word 1: every lane its own word; 64: a whole
+ * wavefront on one word, the pattern of an uncoalesced allocation.  `words`
+ * is a device array of nwords uint64 (contents are overwritten).
+ * lanes_per_word: 1..64.  Asynchronous on `stream`. */
+int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word, uint64_t nthreads,
+                      uint32_t rounds, void* stream);
+
 /* Handle layout: bits 56-63 class id + 1, bits 6-49 block, bits 0-5 slot;
  * 0 is the null handle.  Host-side helpers. */
 uint64_t smmo_ref_make(uint32_t cls, uint64_t block, uint32_t slot);

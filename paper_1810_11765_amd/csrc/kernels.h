@@ -359,6 +359,24 @@ __global__ void k_occupancy(DevHeap h, unsigned long long* out) {
     }
 }
 
+// ------------------------------------------------------- measurement ----
+// Atomic-throughput reference: `rounds` agent-scope 64-bit ORs per thread on
+// word (t / lanes_per_word) % nwords; the returned values are folded into one
+// store per wave so that no OR can be dropped.
+__global__ __launch_bounds__(kBlockThreads) void k_atomic_probe(unsigned long long* words, uint64_t nwords,
+                                                                 uint32_t lanes_per_word, uint64_t nthreads,
+                                                                 uint32_t rounds) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((global_wave() << 6) >= nthreads) return;          // wave-uniform
+    uint64_t acc = 0;
+    if (t < nthreads) {
+        uint64_t* w = reinterpret_cast<uint64_t*>(words) + (t / lanes_per_word) % nwords;
+        for (uint32_t r = 0; r < rounds; ++r) acc ^= at_or(w, 1ull << ((t + r) & 63));
+    }
+    acc = wave_or(acc);
+    if (lane_id() == 0 && acc == 0x5bd1e995ull) words[0] = acc;   // practically never taken
+}
+
 // -------------------------------------------------------- constructors ----
 struct CtorZero {
     struct Args { uint64_t unused; };

@@ -619,6 +619,18 @@ int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream) 
     return SMMO_OK;
 }
 
+int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word, uint64_t nthreads, uint32_t rounds,
+                      void* stream) {
+    if (!words || nwords == 0) return fail(SMMO_EINVAL, "atomic probe: null or empty word array");
+    if (lanes_per_word < 1 || lanes_per_word > 64) return fail(SMMO_EINVAL, "lanes_per_word must be 1..64");
+    if (nthreads == 0 || rounds == 0) return SMMO_OK;
+    if (nthreads > (1ull << 32)) return fail(SMMO_EINVAL, "nthreads too large");
+    k_atomic_probe<<<grid_for(nthreads, kBlockThreads), kBlockThreads, 0, S(stream)>>>(
+        reinterpret_cast<unsigned long long*>(words), nwords, lanes_per_word, nthreads, rounds);
+    LAUNCH_CHECK("k_atomic_probe");
+    return SMMO_OK;
+}
+
 int smmo_occupancy(smmo_heap* heap, uint64_t* used, uint64_t* slots, uint64_t* blocks, void* stream) {
     if (!heap) return fail(SMMO_EINVAL, "null heap");
     if (!used || !slots || !blocks) return fail(SMMO_EINVAL, "null output array");

@@ -125,6 +125,7 @@ def lib():
             "smmo_parallel_do": ([P, u32, u32, P, u64, P], i),
             "smmo_parallel_destroy": ([P, P, u64, u32, P], i),
             "smmo_occupancy": ([P, P, P, P, P], i),
+            "smmo_atomic_probe": ([P, u64, u32, u64, u32, P], i),
             "smmo_live_count": ([P, u32, P, P], i),
             "smmo_dump_objects": ([P, u32, P, u64, P, P], i),
             "smmo_dump_refs": ([P, u32, P, u64, P, P], i),
@@ -333,6 +334,14 @@ class Heap:
         buf = np.zeros(nb.value, dtype=np.uint8)
         check(lib().smmo_dump_raw(self.h, buf.ctypes.data, nb.value, _stream(stream)))
         return buf.tobytes()
+
+
+def atomic_probe(words, lanes_per_word: int, nthreads: int, rounds: int, stream=None) -> None:
+    """Atomic-throughput reference kernel (see smmo_atomic_probe) on a device
+    int64 tensor `words`."""
+    assert words.element_size() == 8 and words.is_contiguous()
+    check(lib().smmo_atomic_probe(words.data_ptr(), words.numel(), lanes_per_word, nthreads, rounds,
+                                  _stream(stream)))
 
 
 def ctor_none(ref_out=None) -> CtorNone:
