@@ -47,10 +47,10 @@ def _occupancy_matches_dump(heap, summary):
     return occ
 
 
-# 270,000 blocks: 4,219 level-0 words, above the word-list threshold of 4,096
+# 270,000 blocks: 4,219 level-0 words, above the block-list threshold of 4,096
 @pytest.mark.parametrize("flat", [False, True])
 def test_wator_big_heap_parity(flat):
-    say("wator big heap", "flat" if flat else "word list")
+    say("wator big heap", "flat" if flat else "block list")
     w = W().WaTor(seed=11, width=193, height=97, num_blocks=270_000)
     if flat:
         w.heap.set_tuning(S().TUNE_FLAT_ENUM)
@@ -142,3 +142,52 @@ def test_raw_alloc_full_size_then_destroy():
     assert ls.heap.live_count(0) == 0
     occ = ls.heap.occupancy()
     assert occ["blocks"] == [0] and ls.heap.status() == 0
+
+
+def test_atomic_probe_sets_every_bit_it_targets():
+    """The atomic-throughput reference kernel: thread t ORs bit (t + r) & 63
+    into word (t / lanes) % nwords for r < rounds."""
+    say("atomic probe")
+    S_ = S()
+    for lanes, nwords, nthreads, rounds in ((1, 1000, 3000, 2), (64, 7, 64 * 20 + 5, 3)):
+        words = torch.zeros(nwords, dtype=torch.int64, device="cuda")
+        S_.atomic_probe(words, lanes, nthreads, rounds)
+        got = words.cpu().numpy().view(np.uint64)
+        want = np.zeros(nwords, dtype=np.uint64)
+        for t in range(nthreads):
+            for r in range(rounds):
+                want[(t // lanes) % nwords] |= np.uint64(1) << np.uint64((t + r) & 63)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("M", [1, 2, 65, 4097, 262145])
+def test_empty_class_and_fill_to_capacity_twice(M):
+    """Degenerate cases on heaps of one to 262,145 blocks (one bitmap level up
+    to three, flat scan and level-1 block list): zero-sized operations, a
+    do-all over a class with no object, then device allocation of every slot
+    of one class and destruction by handle, twice (the second round re-uses
+    invalidated blocks)."""
+    say("edges", M)
+    S_ = S()
+    h = S_.Heap([[4, 4, 4], [8]], M)                      # capacities 42 and 64
+    cap = h.capacity(0) * M
+    visits = torch.zeros(8, dtype=torch.int32, device="cuda")
+    h.parallel_do(0, S_.M_VISIT, S_.VisitArgs(visits.data_ptr()))
+    h.parallel_do(1, S_.M_DESTROY_ALL)
+    refs = torch.zeros(cap, dtype=torch.int64, device="cuda")
+    h.parallel_new(0, 0)
+    h.parallel_alloc(0, 0, 1)
+    h.parallel_destroy(refs, 0, 1)
+    assert int(visits.sum()) == 0 and h.live_count(0) == 0 and h.live_count(1) == 0
+    occ = h.occupancy()
+    assert occ["blocks"] == [0, 0] and occ["F"] == 0.0
+    for _ in range(2):
+        refs.zero_()
+        h.parallel_alloc(0, cap, 1, S_.CTOR_NONE, S_.ctor_none(refs))
+        r = refs.cpu().numpy().view(np.uint64)
+        assert (r != 0).all() and np.unique(r).size == cap
+        summary = check_heap(h, expect_live=[cap, 0])
+        assert summary["free"] == 0 and h.occupancy()["F"] == 0.0
+        h.parallel_destroy(refs, cap, 1)
+        summary = check_heap(h, expect_live=[0, 0])
+        assert summary["free"] == M
