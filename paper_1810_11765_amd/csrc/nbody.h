@@ -264,17 +264,24 @@ __global__ __launch_bounds__(256) void k_nbody_force(DevHeap h, uint32_t cls, co
             tile[e] = v;
         }
         __syncthreads();
+        // Every entry is computed and the sums take it or keep their value
+        // (a select, so the order and the rounding of the additions are
+        // exactly those of the skip-form loop): no branch between entries,
+        // so the compiler can issue one 16-B LDS read per entry and several
+        // entries' reads ahead of their use.  Skipped entries (an empty slot,
+        // or body i itself) may produce inf or NaN in s; it is never used.
         const uint32_t ne = (uint32_t)((r - t0 < kTile ? r - t0 : kTile) * 64);
+#pragma unroll 4
         for (uint32_t e = 0; e < ne; ++e) {
             const float4 v = tile[e];
             const uint32_t tag = (uint32_t)__float_as_int(v.w);
-            if (tag != 0 && tag - 1 != ikey) {
-                const float dx = v.x - xi, dy = v.y - yi;
-                const float d2 = dx * dx + dy * dy;
-                const float s = v.z / (d2 * sqrtf(d2));
-                sx = sx + s * dx;
-                sy = sy + s * dy;
-            }
+            const float dx = v.x - xi, dy = v.y - yi;
+            const float d2 = dx * dx + dy * dy;
+            const float s = v.z / (d2 * sqrtf(d2));
+            const float nx = sx + s * dx, ny = sy + s * dy;
+            const bool use = tag != 0 && tag - 1 != ikey;
+            sx = use ? nx : sx;
+            sy = use ? ny : sy;
         }
     }
     if (me) {
