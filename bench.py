@@ -27,7 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "alloc+destroy Mobj/s; parallel_do GB/s (% HBM peak); app steps/s plain vs batched"
+TUNED_LAUNCH = os.path.join(ROOT, "paper_1810_11765_amd", "tuned_launch.json")
 HBM_PEAK_GBS = 8000.0
+HOLD_CYCLES = 1 << 28           # spin-kernel length that holds the stream while launches are queued
 
 
 def parse():
@@ -41,9 +43,11 @@ def parse():
     p.add_argument("--sweep-blocks", type=int, default=1 << 21)
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
-    p.add_argument("--suite", choices=["ablation", "linux-scalability", "heap-size"],
+    p.add_argument("--suite", choices=["ablation", "linux-scalability", "heap-size", "autotune"],
                    help="run one of the allocator studies instead of the headline and print its JSON line")
     p.add_argument("--suite-steps", type=int, default=None, help="predator-prey steps of a suite run")
+    p.add_argument("--tune-cache", default=None, help="JSON cache the autotune suite writes "
+                   "(default: paper_1810_11765_amd/tuned_launch.json, which the batch sub-measurement reads)")
     return p.parse_args()
 
 
@@ -69,15 +73,24 @@ class Timer:
 
 def life_bench(torch, workloads, steps, warmup):
     from paper_1810_11765_amd import smmo as S
+    from paper_1810_11765_amd import tune
+    # launch shape found by the autotuner for this workload on this device
+    # (bench.py --suite autotune), if the package holds one
+    launch = tune.load(TUNED_LAUNCH, "life-like 512x512 200 steps") or {}
+
+    def grid():
+        g = workloads.LifeGrid(seed=42)
+        g.heap.set_launch(**launch)
+        return g
     if warmup:
-        g0 = workloads.LifeGrid(seed=42)
+        g0 = grid()
         g0.populate()
         for _ in range(warmup):
             g0.step()
         torch.cuda.synchronize()
         del g0
     # eager: K whole steps launched one do-all at a time
-    ge = workloads.LifeGrid(seed=42)
+    ge = grid()
     ge.populate()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -87,7 +100,7 @@ def life_bench(torch, workloads, steps, warmup):
     ms_eager = (time.perf_counter() - t0) * 1e3 / steps
     # timed region: the same K steps captured once in a HIP graph (capture runs
     # nothing), then replayed from the freshly populated state
-    g = workloads.LifeGrid(seed=42)
+    g = grid()
     g.populate()
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
@@ -105,17 +118,28 @@ def life_bench(torch, workloads, steps, warmup):
     same = all((a == b).all() for a, b in zip(g.state(), ge.state()))
     del graph
     # per-kernel durations: the same K steps again from a fresh grid, each
-    # do-all bracketed by events on the stream it is launched on
-    g2 = workloads.LifeGrid(seed=42)
+    # do-all bracketed by events on the stream it is launched on.  A spin
+    # kernel first holds the stream while the host queues every launch, so
+    # the GPU then runs them back to back and an event pair measures the
+    # kernel, not the host's launch latency (a do-all takes less time than its
+    # Python launch path).
+    g2 = grid()
     g2.populate()
+    torch.cuda.synchronize()
+    hold_start = torch.cuda.Event()
+    torch.cuda._sleep(HOLD_CYCLES)
+    hold_start.record()
     tm = Timer(torch)
     for _ in range(steps):
         tm.run("plan", lambda: g2.heap.parallel_do(g2.CELL, S.M_LIFE_PLAN, g2.args))
         tm.run("agent", lambda: g2.heap.parallel_do(g2.AGENT, S.M_LIFE_AGENT, g2.args))
         tm.run("commit", lambda: g2.heap.parallel_do(g2.CELL, S.M_LIFE_COMMIT, g2.args))
+    queued_ahead = not hold_start.query()            # the spin was still running when the last launch was queued
     torch.cuda.synchronize()
     per = {k: sum(tm.ms(k)) / steps for k in ("plan", "agent", "commit")}
-    return ms_step, per, status, {"eager_steps_s": round(1e3 / ms_eager, 2), "graph_equals_eager": bool(same)}
+    return ms_step, per, status, {"eager_steps_s": round(1e3 / ms_eager, 2), "graph_equals_eager": bool(same),
+                                  "launch": g.heap.get_launch(), "events_queued_ahead": queued_ahead,
+                                  "kernel_max_ms": {k: round(max(tm.ms(k)), 5) for k in ("plan", "agent", "commit")}}
 
 
 def roofline_for(per_ms):
@@ -277,7 +301,9 @@ def nbody_sub(torch, workloads, steps=2):
 def sweep_sub(torch, nblocks):
     """parallel_do sweep v += 0.5*x over nblocks x 64 objects of 12 B."""
     from paper_1810_11765_amd import smmo as S
+    from paper_1810_11765_amd import tune
     h = S.Heap([[4, 4, 4]], nblocks)
+    h.set_launch(**(tune.load(TUNED_LAUNCH, "sweep 2^21 blocks") or {}))
     n = nblocks * 64
     h.parallel_new(0, n, S.CTOR_ZERO)
     args = S.AxpyArgs(0.5, 1, 2, 0)
@@ -308,6 +334,7 @@ def sweep_sub(torch, nblocks):
     torch.cuda.synchronize()
     ms_half = sorted(tm2.ms("sweep"))[10]
     status = h.status()
+    h_launch = h.get_launch()
     del h
     # reference: the vendor elementwise kernel on the same access mix (two
     # 512 MiB float reads, one 512 MiB write), i.e. what plain arrays reach
@@ -324,7 +351,9 @@ def sweep_sub(torch, nblocks):
     ref_gbs = 3.0 * a.numel() * 4 / (ref_ms * 1e-3) / 1e9
     del a, b, c
     return {"objects": n, "bytes_per_sweep": 12 * n, "ms_median": round(ms, 4), "gbs": round(gbs, 1),
-            "kernel": "k_doall_axpy<4>", "traffic": measured_traffic("k_doall_axpy<4>@2^21"),
+            "launch": {k: v for k, v in h_launch.items() if k.startswith("sweep")},
+            "kernel": "k_doall_axpy<%d>" % h_launch["sweep_groups"],
+            "traffic": measured_traffic("k_doall_axpy<%d>@2^21" % h_launch["sweep_groups"]),
             "plain_array_reference_gbs": round(ref_gbs, 1),
             "fraction_of_plain_array_reference": round(gbs / ref_gbs, 3),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -342,22 +371,33 @@ def batch_sub(torch, steps=200, count=256):
     import numpy as np
     from paper_1810_11765_amd import serve as sv
     from paper_1810_11765_amd import smmo as S
+    from paper_1810_11765_amd import tune
     reqs = sv.make_requests(seed=42, count=count)
     arena = S.Arena(sv.arena_bytes_for(reqs))
     inst_steps = count * steps
+    # launch shape found by the autotuner for this workload on this device
+    # (bench.py --suite autotune), if the package holds one
+    tuned = tune.load(TUNED_LAUNCH, "predator-prey batched %d instances %d steps" % (count, steps)) or \
+        {"wg_per_cu": 0, "steps_per_launch": 1}
     plain, t_plain = sv.run_plain(reqs, steps, arena)
-    batched, t_batch, _ = sv.run_batched(reqs, steps, arena, per_launch=1, graph=True)
-    served = sv.serve(reqs, steps, arena, time_scale=1.0)
+    base, t_base, grid_base = sv.run_batched(reqs, steps, arena, per_launch=1, graph=True)
+    batched, t_batch, grid = sv.run_batched(reqs, steps, arena, per_launch=tuned["steps_per_launch"], graph=True,
+                                            wg_per_cu=tuned["wg_per_cu"])
+    served = sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"])
     same = all(
         all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], batched[r.rid][0])) and
+        all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], base[r.rid][0])) and
         all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], served["results"][r.rid][0]))
         for r in reqs)
     status = max([plain[r.rid][1] for r in reqs] + [batched[r.rid][1] for r in reqs] +
-                 [served["results"][r.rid][1] for r in reqs])
+                 [base[r.rid][1] for r in reqs] + [served["results"][r.rid][1] for r in reqs])
     lat = served["latency_ms"]
     return {"instances": count, "steps": steps, "cells_total": int(sum(r.side * r.side for r in reqs)),
             "plain_steps_s": round(inst_steps / t_plain, 1),
             "batched_graph_steps_s": round(inst_steps / t_batch, 1),
+            "batched_launch_shape": dict(tuned, workgroups=grid),
+            "batched_default_shape_steps_s": round(inst_steps / t_base, 1),
+            "batched_default_workgroups": grid_base,
             "batched_over_plain": round(t_plain / t_batch, 2),
             "served_wall_s": round(served["wall_s"], 3), "served_busy_s": round(served["busy_s"], 3),
             "served_steps_s": round(inst_steps / served["wall_s"], 1),
@@ -523,11 +563,108 @@ def heap_size_suite(torch, workloads, steps):
     return {"workload": f"predator-prey {side}x{side} torus, seed {seed}, {steps} steps", "rows": rows}
 
 
+def autotune_suite(torch, workloads, cache):
+    """The autotuner (paper_1810_11765_amd/tune.py) on three workloads:
+    the batched predator-prey form of config 5 (workgroups per CU of the
+    persistent kernel, steps per launch), the Life-like step (do-all grid cap and unit
+    count) and the 2^21-block sweep (grid and blocks in flight).  Every
+    candidate's result is compared with the default shape's."""
+    import numpy as np
+    from paper_1810_11765_amd import serve as sv
+    from paper_1810_11765_amd import smmo as S
+    from paper_1810_11765_amd import tune
+    out = {"arch": tune.device_arch()}
+
+    # batched predator-prey (config 5: 256 instances x 200 steps), graph replay
+    reqs = sv.make_requests(seed=42, count=256)
+    arena = S.Arena(sv.arena_bytes_for(reqs))
+
+    def batched(cfg):
+        _progress("autotune batched", cfg)
+        res, dt, grid = sv.run_batched(reqs, 200, arena, per_launch=cfg["steps_per_launch"], graph=True,
+                                       wg_per_cu=cfg["wg_per_cu"])
+        return dt, res
+
+    def same_states(a, b):
+        return all(all(np.array_equal(x, y) for x, y in zip(a[k][0], b[k][0])) and a[k][1] == b[k][1] == 0
+                   for k in a)
+    rec = tune.search(batched, {"wg_per_cu": [0, 1, 2, 3], "steps_per_launch": [1, 2, 5, 10]}, reps=2,
+                      equal=same_states)
+    tune.save(cache, "predator-prey batched 256 instances 200 steps", rec)
+    out["batched"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}
+    out["batched"]["rejected"] = sum(not t["same_result"] for t in rec["trials"])
+    del arena
+
+    # Life-like step: 200 steps, graph replay of the whole run
+    def life(cfg):
+        _progress("autotune life", cfg)
+        g = workloads.LifeGrid(seed=42)
+        g.heap.set_launch(**cfg)
+        g.populate()
+        torch.cuda.synchronize()
+        graph, side = torch.cuda.CUDAGraph(), torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                for _ in range(200):
+                    g.step(stream=side)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = g.state()
+        del graph
+        return dt, (st, g.heap.status())
+
+    def same_life(a, b):
+        return all(np.array_equal(x, y) for x, y in zip(a[0], b[0])) and a[1] == b[1] == 0
+    rec = tune.search(life, {"doall_waves_per_cu": [32, 16, 48, 64], "doall_units": [16384, 4096, 8192, 32768, 65536]},
+                      reps=3, equal=same_life)
+    tune.save(cache, "life-like 512x512 200 steps", rec)
+    out["life"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}
+    out["life"]["rejected"] = sum(not t["same_result"] for t in rec["trials"])
+
+    # sweep at 2^21 blocks (timing) with the result checked on a 2^14-block heap
+    big = S.Heap([[4, 4, 4]], 1 << 21)
+    big.parallel_new(0, (1 << 21) * 64, S.CTOR_ZERO)
+    small = S.Heap([[4, 4, 4]], 1 << 14)
+    n_small = (1 << 14) * 64 - 77
+    xs = torch.arange(n_small, dtype=torch.float32, device="cuda") * 0.125
+    args = S.AxpyArgs(0.5, 1, 2, 0)
+
+    def sweep(cfg):
+        _progress("autotune sweep", cfg)
+        big.set_launch(**cfg)
+        for _ in range(2):
+            big.parallel_do(0, S.M_AXPY, args)
+        tm = Timer(torch)
+        for _ in range(10):
+            tm.run("s", lambda: big.parallel_do(0, S.M_AXPY, args))
+        torch.cuda.synchronize()
+        small.reset()
+        small.set_launch(**cfg)
+        small.parallel_new(0, n_small, S.CTOR_ARRAYS, S.ctor_arrays([None, xs, None]))
+        small.parallel_do(0, S.M_AXPY, args)
+        small.parallel_do(0, S.M_AXPY, args)
+        return sorted(tm.ms("s"))[5] * 1e-3, small.dump_objects(0, [np.int32, np.float32, np.float32])[2]
+
+    rec = tune.search(sweep, {"sweep_waves_per_cu": [128, 32, 64, 256], "sweep_groups": [4, 1, 2]}, reps=1,
+                      equal=lambda a, b: bool(np.array_equal(a, b)))
+    tune.save(cache, "sweep 2^21 blocks", rec)
+    out["sweep"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}
+    out["sweep"]["best_gbs"] = round(12.0 * (1 << 27) / rec["best_s"] / 1e9, 1)
+    out["sweep"]["rejected"] = sum(not t["same_result"] for t in rec["trials"])
+    out["cache"] = cache
+    return out
+
+
 def run_suite(args, torch, workloads):
     if args.suite == "ablation":
         res = ablation_suite(torch, workloads, args.suite_steps or 500)
     elif args.suite == "linux-scalability":
         res = linux_scalability_suite(torch, workloads)
+    elif args.suite == "autotune":
+        res = autotune_suite(torch, workloads, args.tune_cache or TUNED_LAUNCH)
     else:
         res = heap_size_suite(torch, workloads, args.suite_steps or 100)
     print(json.dumps({"suite": args.suite, **res}), flush=True)

@@ -446,6 +446,34 @@ int smmo_batch_step(smmo_batch* batch, uint32_t steps, void* stream);
 int smmo_batch_remaining(smmo_batch* batch, uint32_t* out, void* stream);
 /* Workgroups of the persistent kernel (the occupancy-bounded grid). */
 int smmo_batch_grid(const smmo_batch* batch, uint32_t* workgroups);
+/* Use wg_per_cu workgroups per CU for the persistent kernel (0: as many as
+ * can be resident, the default); more than can be resident is capped.  The
+ * schedule is rebuilt at the next step.  Results do not depend on it. */
+int smmo_batch_set_grid(smmo_batch* batch, uint32_t wg_per_cu);
+
+/* ------------------------------------------------------ launch shape ---- */
+
+/* Launch shape of a heap's kernels.  The paper leaves the do-all's thread
+ * count to hand tuning (Sec. 3.7); here it is a per-heap setting that an
+ * autotuner can search.  Results do not depend on it.  A zero field selects
+ * the built-in default. */
+typedef struct smmo_launch {
+    uint32_t doall_waves_per_cu;   /* do-all grid cap in waves per CU: 1..64 (default 32) */
+    uint32_t doall_units;          /* units of block bits a flat do-all is cut into, at most
+                                      (64 bits per level-0 word) x 64: 64..2^20 (default 16384) */
+    uint32_t list_min_words;       /* level-0 words from which a do-all enumerates through
+                                      level 1 (block list): 1..2^32-1 (default 4096) */
+    uint32_t sweep_waves_per_cu;   /* streaming sweep (SMMO_M_AXPY) grid in waves per CU:
+                                      1..1024 (default 128) */
+    uint32_t sweep_groups;         /* groups of four blocks in flight per sweep wave: 1, 2 or 4
+                                      (default 4) */
+} smmo_launch;
+
+/* Set the launch shape (fields 0: defaults); out-of-range fields: SMMO_EINVAL
+ * and nothing changes.  Host-side only; takes effect for later launches. */
+int smmo_set_launch(smmo_heap* heap, const smmo_launch* launch);
+/* The effective launch shape (defaults filled in). */
+int smmo_get_launch(const smmo_heap* heap, smmo_launch* out);
 
 /* ------------------------------------------------------- measurement ---- */
 

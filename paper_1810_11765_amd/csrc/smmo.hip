@@ -18,22 +18,19 @@
 
 using namespace smmo;
 
-// Launch shape of the streaming sweep: waves per CU (256 CUs; beyond the
-// resident limit, workgroups wait for a slot) and groups of four blocks in
-// flight per wave.  128 x 4 measured best on MI355X with non-temporal field
-// access (one L0 word per wave at 2^21 blocks).
-#ifndef SMMO_SWEEP_WAVES_PER_CU
-#define SMMO_SWEEP_WAVES_PER_CU 128
-#endif
-#ifndef SMMO_SWEEP_GROUPS
-#define SMMO_SWEEP_GROUPS 4
-#endif
+// Default launch shape (smmo_launch).  Sweep: 128 waves per CU (beyond the
+// resident limit, workgroups wait for a slot) x 4 groups of four blocks in
+// flight measured best on MI355X with non-temporal field access (one L0 word
+// per wave at 2^21 blocks).
+constexpr smmo_launch kDefaultLaunch = {32, 16384, 4096, 128, 4};
 
 struct smmo_heap {
     smmo_raw_header hdr;   // host copy of the device header
     DevHeap dev;           // kernel-argument view
     uint8_t* base;         // caller's device buffer
     uint64_t bytes;
+    smmo_launch launch;    // effective launch shape
+    uint32_t cus;          // compute units of the device
 };
 
 namespace {
@@ -208,16 +205,12 @@ unsigned long long* scratch_counter(smmo_heap* H, int i) {
 // stream-ordered).
 uint32_t* scratch_R(smmo_heap* H) { return reinterpret_cast<uint32_t*>(H->dev.scratch + kScratchHead); }
 
-#ifndef SMMO_LIST_MIN_WORDS
-#define SMMO_LIST_MIN_WORDS 4096   // L0 words from which enumeration goes through level 1
-#endif
-
 // Big heaps: list the blocks of allocated[cls] via level 1 into R, so that
 // the passes after it cost the class's blocks, not the heap's size.
 // Returns false (nothing launched) when the heap is scanned flat.
 bool build_block_list(smmo_heap* H, uint32_t cls, hipStream_t s, int* rc) {
     *rc = SMMO_OK;
-    if (H->hdr.nlevels < 2 || H->hdr.level_words[0] < SMMO_LIST_MIN_WORDS || (H->dev.tune & SMMO_TUNE_FLAT_ENUM))
+    if (H->hdr.nlevels < 2 || H->hdr.level_words[0] < H->launch.list_min_words || (H->dev.tune & SMMO_TUNE_FLAT_ENUM))
         return false;
     unsigned long long* cnt = scratch_counter(H, 3);
     k_fill_u64<<<1, 64, 0, s>>>(cnt, 1, 0);
@@ -230,7 +223,7 @@ bool build_block_list(smmo_heap* H, uint32_t cls, hipStream_t s, int* rc) {
 // grid of the list-form thread-per-block passes: at most 32 waves per CU,
 // grid-stride beyond
 unsigned list_grid(const smmo_heap* H) {
-    const uint64_t threads = std::min<uint64_t>(H->hdr.num_blocks, 256ull * 32 * 64);
+    const uint64_t threads = std::min<uint64_t>(H->hdr.num_blocks, (uint64_t)H->cus * 32 * 64);
     return grid_for(threads, 256);
 }
 
@@ -253,14 +246,15 @@ int unpack_args(A& a, const void* args, uint64_t bytes, const char* what) {
 }
 
 // units of 64 >> s_log2 block bits so that small heaps still spread over
-// enough waves; big heaps get whole words per unit and a capped grid
+// enough waves (launch.doall_units); big heaps get whole words per unit and
+// a grid capped at launch.doall_waves_per_cu
 void doall_geometry(const smmo_heap* H, uint32_t& s_log2, uint64_t& nunits, unsigned& grid) {
     const uint64_t W0 = H->hdr.level_words[0];
-    const uint64_t target = 16384;                         // waves wanted in flight
+    const uint64_t target = H->launch.doall_units;
     s_log2 = 0;
     while (s_log2 < 6 && (W0 << s_log2) < target) ++s_log2;
     nunits = W0 << s_log2;
-    const uint64_t waves = std::min<uint64_t>(nunits, 256ull * 32);
+    const uint64_t waves = std::min<uint64_t>(nunits, (uint64_t)H->cus * H->launch.doall_waves_per_cu);
     grid = (unsigned)((waves + 3) / 4);
 }
 
@@ -299,7 +293,8 @@ int launch_doall_one(smmo_heap* H, uint32_t cls, const typename M::Args& a, bool
         // runs to at most 16,384 of them; the grid covers that many waves or
         // one per listed block, whichever is less, at most 32 waves per CU
         nunits = 0;
-        grid = (unsigned)((std::min<uint64_t>(std::min<uint64_t>(H->hdr.num_blocks, 16384), 256ull * 32) + 3) / 4);
+        grid = (unsigned)((std::min<uint64_t>(std::min<uint64_t>(H->hdr.num_blocks, 16384),
+                                              (uint64_t)H->cus * H->launch.doall_waves_per_cu) + 3) / 4);
     }
     k_doall<M, kSnap><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, R, nR, a);
     LAUNCH_CHECK("k_doall");
@@ -432,10 +427,43 @@ int smmo_heap_create(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blo
     }
     H->base = static_cast<uint8_t*>(dev_mem);
     H->bytes = dev_bytes;
+    H->launch = kDefaultLaunch;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+            delete H;
+            return fail(SMMO_EHIP, "cannot query the device's compute units");
+        }
+        H->cus = (uint32_t)cus;
+    }
     fill_dev(H);
     rc = init_device(H, S(stream));
     if (rc) { delete H; return rc; }
     *out = H;
+    return SMMO_OK;
+}
+
+int smmo_set_launch(smmo_heap* heap, const smmo_launch* l) {
+    if (!heap || !l) return fail(SMMO_EINVAL, "null argument");
+    smmo_launch v = *l;
+    if (!v.doall_waves_per_cu) v.doall_waves_per_cu = kDefaultLaunch.doall_waves_per_cu;
+    if (!v.doall_units) v.doall_units = kDefaultLaunch.doall_units;
+    if (!v.list_min_words) v.list_min_words = kDefaultLaunch.list_min_words;
+    if (!v.sweep_waves_per_cu) v.sweep_waves_per_cu = kDefaultLaunch.sweep_waves_per_cu;
+    if (!v.sweep_groups) v.sweep_groups = kDefaultLaunch.sweep_groups;
+    if (v.doall_waves_per_cu > 64) return fail(SMMO_EINVAL, "doall_waves_per_cu must be 1..64");
+    if (v.doall_units < 64 || v.doall_units > (1u << 20)) return fail(SMMO_EINVAL, "doall_units must be 64..2^20");
+    if (v.sweep_waves_per_cu > 1024) return fail(SMMO_EINVAL, "sweep_waves_per_cu must be 1..1024");
+    if (v.sweep_groups != 1 && v.sweep_groups != 2 && v.sweep_groups != 4)
+        return fail(SMMO_EINVAL, "sweep_groups must be 1, 2 or 4");
+    heap->launch = v;
+    return SMMO_OK;
+}
+
+int smmo_get_launch(const smmo_heap* heap, smmo_launch* out) {
+    if (!heap || !out) return fail(SMMO_EINVAL, "null argument");
+    *out = heap->launch;
     return SMMO_OK;
 }
 
@@ -547,10 +575,14 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
             uint32_t cl[SMMO_MAX_CLASSES];
             const uint32_t n = subtree(heap, cls, cl);
             const uint64_t nwords = heap->hdr.level_words[0];
-            const uint64_t waves = std::min<uint64_t>(nwords, 256ull * SMMO_SWEEP_WAVES_PER_CU);
+            const uint64_t waves = std::min<uint64_t>(nwords, (uint64_t)heap->cus * heap->launch.sweep_waves_per_cu);
+            const unsigned grid = (unsigned)((waves + 3) / 4);
             for (uint32_t i = 0; i < n; ++i) {
-                k_doall_axpy<SMMO_SWEEP_GROUPS><<<(unsigned)((waves + 3) / 4), kBlockThreads, 0, s>>>(
-                    heap->dev, cl[i], nwords, a);
+                switch (heap->launch.sweep_groups) {
+                    case 1: k_doall_axpy<1><<<grid, kBlockThreads, 0, s>>>(heap->dev, cl[i], nwords, a); break;
+                    case 2: k_doall_axpy<2><<<grid, kBlockThreads, 0, s>>>(heap->dev, cl[i], nwords, a); break;
+                    default: k_doall_axpy<4><<<grid, kBlockThreads, 0, s>>>(heap->dev, cl[i], nwords, a); break;
+                }
                 LAUNCH_CHECK("k_doall_axpy");
             }
             return SMMO_OK;
@@ -796,7 +828,9 @@ struct smmo_arena {
 struct smmo_batch {
     smmo_arena* arena;
     uint32_t max_inst;
-    uint32_t grid;                              // persistent workgroups
+    uint32_t grid;                              // persistent workgroups in use
+    uint32_t grid_max;                          // all that can be resident (tables sized for it)
+    uint32_t cus, per_cu;                       // compute units, resident workgroups per CU
     uint8_t* dev;                               // device tables (from the arena)
     BatchDesc* d_desc;
     BatchProg* d_prog;
@@ -891,9 +925,11 @@ int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
     B->max_inst = max_inst;
     // every workgroup must be resident at once for the instance barriers: the
     // grid is the occupancy the runtime reports for this kernel (capped)
-    B->grid = (uint32_t)cus * (uint32_t)std::max(1, std::min(per_cu, 8));
+    B->cus = (uint32_t)cus;
+    B->per_cu = (uint32_t)per_cu;
+    B->grid_max = B->grid = (uint32_t)cus * (uint32_t)per_cu;
     const uint64_t bytes = align_up(sizeof(BatchDesc) * max_inst, 256) + align_up(sizeof(BatchProg) * max_inst, 256) +
-                           align_up(sizeof(BatchSched) * max_inst, 256) + align_up(4ull * B->grid, 256) +
+                           align_up(sizeof(BatchSched) * max_inst, 256) + align_up(4ull * B->grid_max, 256) +
                            align_up(4ull * max_inst, 256);
     void* p = nullptr;
     int rc = smmo_arena_alloc(arena, bytes, &p);
@@ -903,7 +939,7 @@ int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
     B->d_desc = reinterpret_cast<BatchDesc*>(q);        q += align_up(sizeof(BatchDesc) * max_inst, 256);
     B->d_prog = reinterpret_cast<BatchProg*>(q);        q += align_up(sizeof(BatchProg) * max_inst, 256);
     B->d_sched = reinterpret_cast<BatchSched*>(q);      q += align_up(sizeof(BatchSched) * max_inst, 256);
-    B->d_wg_inst = reinterpret_cast<int32_t*>(q);       q += align_up(4ull * B->grid, 256);
+    B->d_wg_inst = reinterpret_cast<int32_t*>(q);       q += align_up(4ull * B->grid_max, 256);
     B->d_bar = reinterpret_cast<uint32_t*>(q);
     B->used.assign(max_inst, 0);
     B->weight.assign(max_inst, 0);
@@ -1011,6 +1047,14 @@ int smmo_batch_remaining(smmo_batch* B, uint32_t* out, void* stream) {
 int smmo_batch_grid(const smmo_batch* B, uint32_t* workgroups) {
     if (!B || !workgroups) return fail(SMMO_EINVAL, "null argument");
     *workgroups = B->grid;
+    return SMMO_OK;
+}
+
+int smmo_batch_set_grid(smmo_batch* B, uint32_t wg_per_cu) {
+    if (!B) return fail(SMMO_EINVAL, "null batch");
+    const uint32_t w = wg_per_cu == 0 || wg_per_cu > B->per_cu ? B->per_cu : wg_per_cu;
+    B->grid = B->cus * w;
+    B->dirty = true;
     return SMMO_OK;
 }
 

@@ -114,10 +114,12 @@ def run_plain(reqs, steps: int, arena: S.Arena):
     return results, time.perf_counter() - t0
 
 
-def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bool = False):
-    """All instances admitted, then `steps` steps of the persistent kernel.
-    Returns (results, seconds of the stepping, grid workgroups)."""
+def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bool = False, wg_per_cu: int = 0):
+    """All instances admitted, then `steps` steps of the persistent kernel
+    (`per_launch` steps per launch, wg_per_cu workgroups per CU, 0 = all that
+    fit).  Returns (results, seconds of the stepping, grid workgroups)."""
     fleet = Fleet(arena, max(len(reqs), 1))
+    fleet.batch.set_grid(wg_per_cu)
     for r in reqs:
         assert fleet.admit(r, steps), "arena too small for the whole batch"
     torch.cuda.synchronize()
@@ -143,19 +145,24 @@ def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bo
             fleet.batch.step(per_launch)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+    grid = fleet.batch.grid()
     results = {req.rid: (st, status) for req, st, status in fleet.harvest()}
     assert not fleet.live, "instances left unfinished"
     fleet.close()
-    return results, dt, None
+    return results, dt, grid
 
 
-def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instances: int = 256):
-    """Continuous batching over arrivals (arrival times scaled by time_scale).
+def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instances: int = 256,
+          wg_per_cu: int = 0):
+    """Continuous batching over arrivals (arrival times scaled by time_scale),
+    one persistent-kernel step per launch on wg_per_cu workgroups per CU
+    (0 = all that fit).
 
     Returns dict with results per request, per instance-step latencies (ms),
     wall seconds, busy seconds and admission delays.
     """
     fleet = Fleet(arena, max_instances)
+    fleet.batch.set_grid(wg_per_cu)
     pending = deque(sorted(reqs, key=lambda r: r.arrival))
     lat, admit_delay, results = [], [], {}
     busy = 0.0

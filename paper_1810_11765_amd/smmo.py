@@ -58,6 +58,15 @@ class Layout(C.Structure):
                 ("field_bytes", C.c_uint32 * MAX_FIELDS), ("field_offset", C.c_uint32 * MAX_FIELDS)]
 
 
+class Launch(C.Structure):
+    """smmo_launch: per-heap launch shape (0 = default)."""
+    _fields_ = [("doall_waves_per_cu", C.c_uint32), ("doall_units", C.c_uint32), ("list_min_words", C.c_uint32),
+                ("sweep_waves_per_cu", C.c_uint32), ("sweep_groups", C.c_uint32)]
+
+
+LAUNCH_FIELDS = [f for f, _ in Launch._fields_]
+
+
 class CtorNone(C.Structure):
     _fields_ = [("ref_out", C.c_void_p)]
 
@@ -126,6 +135,8 @@ def lib():
             "smmo_parallel_destroy": ([P, P, u64, u32, P], i),
             "smmo_occupancy": ([P, P, P, P, P], i),
             "smmo_atomic_probe": ([P, u64, u32, u64, u32, P], i),
+            "smmo_set_launch": ([P, P], i),
+            "smmo_get_launch": ([P, P], i),
             "smmo_live_count": ([P, u32, P, P], i),
             "smmo_dump_objects": ([P, u32, P, u64, P, P], i),
             "smmo_dump_refs": ([P, u32, P, u64, P, P], i),
@@ -282,6 +293,18 @@ class Heap:
     def reset(self, stream=None) -> None:
         check(lib().smmo_heap_reset(self.h, _stream(stream)))
 
+    def set_launch(self, **fields) -> None:
+        """Launch shape of this heap's kernels (smmo_launch fields; omitted or 0 =
+        default).  Results do not depend on it."""
+        unknown = set(fields) - set(LAUNCH_FIELDS)
+        assert not unknown, f"unknown launch fields {unknown}"
+        check(lib().smmo_set_launch(self.h, C.byref(Launch(**fields))))
+
+    def get_launch(self) -> dict:
+        out = Launch()
+        check(lib().smmo_get_launch(self.h, C.byref(out)))
+        return {f: getattr(out, f) for f in LAUNCH_FIELDS}
+
     # -- operations
     def parallel_new(self, cls: int, n: int, ctor: int = CTOR_ZERO, args=None, stream=None) -> None:
         p, nb = _blob(args)
@@ -398,7 +421,7 @@ def _bind_batch():
         "smmo_batch_create": ([P, u32, P], i), "smmo_batch_destroy": ([P], i),
         "smmo_batch_add_wator": ([P, P, P, u32, P, P], i), "smmo_batch_remove": ([P, u32], i),
         "smmo_batch_step": ([P, u32, P], i), "smmo_batch_remaining": ([P, P, P], i),
-        "smmo_batch_grid": ([P, P], i),
+        "smmo_batch_grid": ([P, P], i), "smmo_batch_set_grid": ([P, u32], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -479,6 +502,10 @@ class Batch:
         g = C.c_uint32()
         check(lib().smmo_batch_grid(self.h, C.byref(g)))
         return g.value
+
+    def set_grid(self, wg_per_cu: int = 0) -> None:
+        """Workgroups per CU of the persistent kernel (0 = all that fit)."""
+        check(lib().smmo_batch_set_grid(self.h, wg_per_cu))
 
     def close(self):
         if getattr(self, "h", None):

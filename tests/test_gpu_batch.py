@@ -52,6 +52,19 @@ def test_batched_instances_match_oracle(per_launch, graph):
     assert free == largest                                   # every range returned and merged
 
 
+@pytest.mark.parametrize("wg_per_cu", [1, 2])
+def test_batched_smaller_grid_matches_oracle(wg_per_cu):
+    """The persistent kernel on 1 or 2 workgroups per CU (the autotuner's
+    knob): same results."""
+    say("batched grid", wg_per_cu)
+    sv = SV()
+    reqs = sv.make_requests(seed=15, count=12, lo=12, hi=100)
+    arena = S().Arena(sv.arena_bytes_for(reqs))
+    results, dt, grid = sv.run_batched(reqs, 40, arena, per_launch=3, graph=False, wg_per_cu=wg_per_cu)
+    assert grid == 256 * wg_per_cu or grid < 256 * wg_per_cu      # capped by residency
+    _check(results, reqs, 40)
+
+
 def test_plain_one_by_one_matches_oracle():
     say("plain")
     sv = SV()

@@ -191,3 +191,47 @@ def test_empty_class_and_fill_to_capacity_twice(M):
         h.parallel_destroy(refs, cap, 1)
         summary = check_heap(h, expect_live=[0, 0])
         assert summary["free"] == M
+
+
+LAUNCHES = [dict(), dict(doall_waves_per_cu=1, doall_units=64), dict(doall_waves_per_cu=64, doall_units=1 << 20),
+            dict(list_min_words=1), dict(sweep_waves_per_cu=1, sweep_groups=1), dict(sweep_groups=2)]
+
+
+@pytest.mark.parametrize("launch", LAUNCHES, ids=[str(i) for i in range(len(LAUNCHES))])
+def test_launch_shapes_do_not_change_results(launch):
+    """Extreme launch shapes (one wave per CU, 64-bit units, a block list even
+    for a small heap, a one-wave sweep): predator-prey equals the oracle and
+    the sweep gives the same values."""
+    say("launch", launch)
+    S_ = S()
+    w = W().WaTor(seed=31, width=96, height=80, num_blocks=512)
+    w.heap.set_launch(**launch)
+    got = w.heap.get_launch()
+    assert all(got[k] == v for k, v in launch.items())
+    w.populate()
+    for _ in range(40):
+        w.step()
+    wator_check(w, 40, core.c3_run(w.kind0, 96, 80, 31, 40))
+    h = S_.Heap([[4, 4, 4]], 300)
+    h.set_launch(**launch)
+    n = 300 * 64 - 5
+    x = torch.arange(n, dtype=torch.float32, device="cuda") * 0.25
+    h.parallel_new(0, n, S_.CTOR_ARRAYS, S_.ctor_arrays([None, x, None]))
+    for _ in range(3):
+        h.parallel_do(0, S_.M_AXPY, S_.AxpyArgs(0.5, 1, 2, 0))
+    ids, xv, v = h.dump_objects(0, [np.int32, np.float32, np.float32])
+    xs = np.arange(n, dtype=np.float32) * np.float32(0.25)
+    want = np.zeros(n, dtype=np.float32)
+    for _ in range(3):
+        want = want + np.float32(0.5) * xs
+    assert np.array_equal(v, want)
+
+
+def test_launch_shape_rejects_out_of_range():
+    S_ = S()
+    h = S_.Heap([[4]], 8)
+    for bad in (dict(doall_waves_per_cu=65), dict(doall_units=63), dict(sweep_groups=3), dict(sweep_waves_per_cu=2000)):
+        with pytest.raises(S_.SmmoError):
+            h.set_launch(**bad)
+    assert h.get_launch() == {"doall_waves_per_cu": 32, "doall_units": 16384, "list_min_words": 4096,
+                              "sweep_waves_per_cu": 128, "sweep_groups": 4}
