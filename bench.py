@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--sweep-blocks", type=int, default=1 << 21)
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
-    p.add_argument("--suite", choices=["ablation", "linux-scalability", "heap-size", "autotune"],
+    p.add_argument("--suite", choices=["ablation", "linux-scalability", "heap-size", "autotune", "nbody"],
                    help="run one of the allocator studies instead of the headline and print its JSON line")
     p.add_argument("--suite-steps", type=int, default=None, help="predator-prey steps of a suite run")
     p.add_argument("--tune-cache", default=None, help="JSON cache the autotune suite writes "
@@ -665,6 +665,8 @@ def run_suite(args, torch, workloads):
         res = linux_scalability_suite(torch, workloads)
     elif args.suite == "autotune":
         res = autotune_suite(torch, workloads, args.tune_cache or TUNED_LAUNCH)
+    elif args.suite == "nbody":
+        res = {"workload": "n-body with merging, 262,144 bodies, seed 42", **nbody_sub(torch, workloads)}
     else:
         res = heap_size_suite(torch, workloads, args.suite_steps or 100)
     print(json.dumps({"suite": args.suite, **res}), flush=True)
