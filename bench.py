@@ -76,11 +76,14 @@ def life_bench(torch, workloads, steps, warmup):
     from paper_1810_11765_amd import tune
     # launch shape found by the autotuner for this workload on this device
     # (bench.py --suite autotune), if the package holds one
-    launch = tune.load(TUNED_LAUNCH, "life-like 512x512 200 steps") or {}
+    shape = tune.load(TUNED_LAUNCH, "life-like 512x512 200 steps") or {}
+    launch = {k: v for k, v in shape.items() if k in S.LAUNCH_FIELDS}
+    lookups = shape.get("lookups", 5)
 
     def grid():
         g = workloads.LifeGrid(seed=42)
         g.heap.set_launch(**launch)
+        g.heap.set_tuning(0, lookups, 0)
         return g
     if warmup:
         g0 = grid()
@@ -138,7 +141,7 @@ def life_bench(torch, workloads, steps, warmup):
     torch.cuda.synchronize()
     per = {k: sum(tm.ms(k)) / steps for k in ("plan", "agent", "commit")}
     return ms_step, per, status, {"eager_steps_s": round(1e3 / ms_eager, 2), "graph_equals_eager": bool(same),
-                                  "launch": g.heap.get_launch(), "events_queued_ahead": queued_ahead,
+                                  "launch": g.heap.get_launch(), "lookups": lookups, "events_queued_ahead": queued_ahead,
                                   "kernel_max_ms": {k: round(max(tm.ms(k)), 5) for k in ("plan", "agent", "commit")}}
 
 
@@ -377,13 +380,13 @@ def batch_sub(torch, steps=200, count=256):
     inst_steps = count * steps
     # launch shape found by the autotuner for this workload on this device
     # (bench.py --suite autotune), if the package holds one
-    tuned = tune.load(TUNED_LAUNCH, "predator-prey batched %d instances %d steps" % (count, steps)) or \
-        {"wg_per_cu": 0, "steps_per_launch": 1}
+    tuned = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5}
+    tuned.update(tune.load(TUNED_LAUNCH, "predator-prey batched %d instances %d steps" % (count, steps)) or {})
     plain, t_plain = sv.run_plain(reqs, steps, arena)
     base, t_base, grid_base = sv.run_batched(reqs, steps, arena, per_launch=1, graph=True)
     batched, t_batch, grid = sv.run_batched(reqs, steps, arena, per_launch=tuned["steps_per_launch"], graph=True,
-                                            wg_per_cu=tuned["wg_per_cu"])
-    served = sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"])
+                                            wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"])
+    served = sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"])
     same = all(
         all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], batched[r.rid][0])) and
         all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], base[r.rid][0])) and
@@ -566,8 +569,9 @@ def heap_size_suite(torch, workloads, steps):
 def autotune_suite(torch, workloads, cache):
     """The autotuner (paper_1810_11765_amd/tune.py) on three workloads:
     the batched predator-prey form of config 5 (workgroups per CU of the
-    persistent kernel, steps per launch), the Life-like step (do-all grid cap and unit
-    count) and the 2^21-block sweep (grid and blocks in flight).  Every
+    persistent kernel, steps per launch, active-block lookups r), the
+    Life-like step (r, do-all grid cap and unit count) and the 2^21-block
+    sweep (grid and blocks in flight).  Every
     candidate's result is compared with the default shape's."""
     import numpy as np
     from paper_1810_11765_amd import serve as sv
@@ -582,14 +586,14 @@ def autotune_suite(torch, workloads, cache):
     def batched(cfg):
         _progress("autotune batched", cfg)
         res, dt, grid = sv.run_batched(reqs, 200, arena, per_launch=cfg["steps_per_launch"], graph=True,
-                                       wg_per_cu=cfg["wg_per_cu"])
+                                       wg_per_cu=cfg["wg_per_cu"], lookups=cfg["lookups"])
         return dt, res
 
     def same_states(a, b):
         return all(all(np.array_equal(x, y) for x, y in zip(a[k][0], b[k][0])) and a[k][1] == b[k][1] == 0
                    for k in a)
-    rec = tune.search(batched, {"wg_per_cu": [0, 1, 2, 3], "steps_per_launch": [1, 2, 5, 10]}, reps=2,
-                      equal=same_states)
+    rec = tune.search(batched, {"wg_per_cu": [0, 1, 2, 3], "steps_per_launch": [1, 2, 5, 10],
+                                "lookups": [5, 3, 8, 12]}, reps=2, equal=same_states)
     tune.save(cache, "predator-prey batched 256 instances 200 steps", rec)
     out["batched"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}
     out["batched"]["rejected"] = sum(not t["same_result"] for t in rec["trials"])
@@ -599,7 +603,8 @@ def autotune_suite(torch, workloads, cache):
     def life(cfg):
         _progress("autotune life", cfg)
         g = workloads.LifeGrid(seed=42)
-        g.heap.set_launch(**cfg)
+        g.heap.set_launch(**{k: v for k, v in cfg.items() if k in S.LAUNCH_FIELDS})
+        g.heap.set_tuning(0, cfg["lookups"], 0)
         g.populate()
         torch.cuda.synchronize()
         graph, side = torch.cuda.CUDAGraph(), torch.cuda.Stream()
@@ -618,8 +623,8 @@ def autotune_suite(torch, workloads, cache):
 
     def same_life(a, b):
         return all(np.array_equal(x, y) for x, y in zip(a[0], b[0])) and a[1] == b[1] == 0
-    rec = tune.search(life, {"doall_waves_per_cu": [32, 16, 48, 64], "doall_units": [16384, 4096, 8192, 32768, 65536]},
-                      reps=3, equal=same_life)
+    rec = tune.search(life, {"lookups": [5, 3, 8, 12, 16], "doall_waves_per_cu": [32, 16, 48, 64],
+                             "doall_units": [16384, 4096, 8192, 32768, 65536]}, reps=5, equal=same_life)
     tune.save(cache, "life-like 512x512 200 steps", rec)
     out["life"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}
     out["life"]["rejected"] = sum(not t["same_result"] for t in rec["trials"])

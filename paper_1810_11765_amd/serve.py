@@ -64,9 +64,10 @@ def instance_state(w: WaTor):
 class Fleet:
     """A batch plus the instances it runs."""
 
-    def __init__(self, arena: S.Arena, max_instances: int = 256):
+    def __init__(self, arena: S.Arena, max_instances: int = 256, lookups: int = 5):
         self.arena = arena
         self.batch = S.Batch(arena, max_instances)
+        self.lookups = lookups              # active-block lookups r of every instance heap
         self.live = {}                      # slot -> (request, WaTor)
 
     def admit(self, req: Request, steps: int, stream=None) -> bool:
@@ -75,6 +76,8 @@ class Fleet:
                       arena=self.arena)
         except S.SmmoError:
             return False                    # no room in the arena yet
+        if self.lookups != 5:
+            w.heap.set_tuning(0, self.lookups, 0, stream=stream)
         w.populate(stream)
         slot = self.batch.add(w.heap, w.args, steps, stream)
         self.live[slot] = (req, w)
@@ -114,11 +117,13 @@ def run_plain(reqs, steps: int, arena: S.Arena):
     return results, time.perf_counter() - t0
 
 
-def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bool = False, wg_per_cu: int = 0):
+def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bool = False, wg_per_cu: int = 0,
+                lookups: int = 5):
     """All instances admitted, then `steps` steps of the persistent kernel
     (`per_launch` steps per launch, wg_per_cu workgroups per CU, 0 = all that
-    fit).  Returns (results, seconds of the stepping, grid workgroups)."""
-    fleet = Fleet(arena, max(len(reqs), 1))
+    fit; `lookups` active-block lookups per allocation).  Returns (results,
+    seconds of the stepping, grid workgroups)."""
+    fleet = Fleet(arena, max(len(reqs), 1), lookups=lookups)
     fleet.batch.set_grid(wg_per_cu)
     for r in reqs:
         assert fleet.admit(r, steps), "arena too small for the whole batch"
@@ -153,7 +158,7 @@ def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bo
 
 
 def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instances: int = 256,
-          wg_per_cu: int = 0):
+          wg_per_cu: int = 0, lookups: int = 5):
     """Continuous batching over arrivals (arrival times scaled by time_scale),
     one persistent-kernel step per launch on wg_per_cu workgroups per CU
     (0 = all that fit).
@@ -161,7 +166,7 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
     Returns dict with results per request, per instance-step latencies (ms),
     wall seconds, busy seconds and admission delays.
     """
-    fleet = Fleet(arena, max_instances)
+    fleet = Fleet(arena, max_instances, lookups=lookups)
     fleet.batch.set_grid(wg_per_cu)
     pending = deque(sorted(reqs, key=lambda r: r.arrival))
     lat, admit_delay, results = [], [], {}
