@@ -181,10 +181,10 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE and
-    WRITE_SIZE runs recorded in profiles/traffic.json (each counter scaled by
+    WRITE_SIZE runs recorded in paper_1810_11765_amd/hbm_traffic.json (each counter scaled by
     its reading on a plain copy of known size), or None when that record was
     taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "paper_1810_11765_amd", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
