@@ -48,6 +48,26 @@ def test_life_full_size_parity(seed):
     _life_check(g, 512, 512, 200)
 
 
+def test_life_full_size_parity_with_the_tuned_shape():
+    """The launch shape and active-block lookups the bench uses for the
+    Life-like headline (autotuner's cache), 200 steps at full size."""
+    import os
+    from paper_1810_11765_amd import smmo as S
+    from paper_1810_11765_amd import tune
+    path = os.path.join(os.path.dirname(S.__file__), "tuned_launch.json")
+    shape = tune.load(path, "life-like 512x512 200 steps")
+    if shape is None:
+        pytest.skip("no tuned shape for this device")
+    say("life tuned", shape)
+    g = W().LifeGrid(seed=42)
+    g.heap.set_launch(**{k: v for k, v in shape.items() if k in S.LAUNCH_FIELDS})
+    g.heap.set_tuning(0, shape.get("lookups", 5), 0)
+    g.populate()
+    for _ in range(200):
+        g.step()
+    _life_check(g, 512, 512, 200)
+
+
 @pytest.mark.parametrize("Wd,Hd,blocks", [(37, 23, 64), (130, 7, 64), (64, 64, 128)])
 def test_life_ragged_parity(Wd, Hd, blocks):
     say("life ragged", Wd, Hd)

@@ -65,6 +65,24 @@ def test_batched_smaller_grid_matches_oracle(wg_per_cu):
     _check(results, reqs, 40)
 
 
+def test_batched_with_the_tuned_shape_matches_oracle():
+    """The launch shape the bench uses for config 5 (autotuner's cache):
+    workgroups per CU, steps per launch and active-block lookups."""
+    import os
+    from paper_1810_11765_amd import tune
+    path = os.path.join(os.path.dirname(SV().__file__), "tuned_launch.json")
+    shape = tune.load(path, "predator-prey batched 256 instances 200 steps")
+    if shape is None:
+        pytest.skip("no tuned shape for this device")
+    say("batched tuned", shape)
+    sv = SV()
+    reqs = sv.make_requests(seed=17, count=24, lo=16, hi=160)
+    arena = S().Arena(sv.arena_bytes_for(reqs))
+    results, dt, grid = sv.run_batched(reqs, 50, arena, per_launch=shape["steps_per_launch"], graph=True,
+                                       wg_per_cu=shape["wg_per_cu"], lookups=shape.get("lookups", 5))
+    _check(results, reqs, 50)
+
+
 def test_plain_one_by_one_matches_oracle():
     say("plain")
     sv = SV()
