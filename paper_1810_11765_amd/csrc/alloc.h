@@ -104,6 +104,10 @@ __device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t 
             bid = bm_try_find_set(h, bm_active(h, cls), seed);
             if (bid != kFail) break;
             count(h, SMMO_CNT_FIND_FAIL);
+            // a request for a whole block or more fills a fresh block by
+            // itself, so retrying the lookup cannot save a block: one miss
+            // sends it to the slow path
+            if (want >= h.cls_cap[cls]) break;
         }
         if (bid == kFail) {                               // slow path
             bid = bm_clear_any(h, bm_free(), seed);
