@@ -36,10 +36,12 @@ constexpr uint32_t kAllocIters = 1u << 18;
 // initialize_block<T> (Alg. 8): type first, then (after a release) the words.
 // The iteration word is zeroed as well, so a block re-initialized during a
 // do-all is never visited by it.
-__device__ inline void initialize_block(const DevHeap& h, uint32_t cls, uint64_t bid) {
+// With `word` the allocation word starts as given instead of the padding
+// (all ones: a block whose every slot goes to the caller).
+__device__ inline void initialize_block(const DevHeap& h, uint32_t cls, uint64_t bid, uint64_t word) {
     at_store32(&h.type[bid], cls);
     at_store(&h.iter[bid], 0);
-    at_store_rel(&h.alloc[bid], h.cls_pad[cls]);
+    at_store_rel(&h.alloc[bid], word);
 }
 
 // invalidate(bid) (Alg. 9, iterative).  True if this call took the block
@@ -119,10 +121,21 @@ __device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t 
                 backoff();
                 continue;
             }
-            initialize_block(h, cls, bid);
+            count(h, SMMO_CNT_BLOCK_INIT);
+            if (want >= h.cls_cap[cls]) {
+                // the whole block goes to this request: it starts full and
+                // never becomes active (no other wave can find it before
+                // allocated[cls] lists it, and by then it is full), which
+                // saves the reservation and two active-bitmap updates
+                initialize_block(h, cls, bid, kOnes);
+                bm_set(h, bm_allocated(cls), bid);
+                empty_rounds = 0;
+                bid_out = bid;
+                return ~h.cls_pad[cls];
+            }
+            initialize_block(h, cls, bid, h.cls_pad[cls]);
             bm_set(h, bm_allocated(cls), bid);
             bm_set(h, bm_active(h, cls), bid);
-            count(h, SMMO_CNT_BLOCK_INIT);
         }
         if (h.tune & SMMO_TUNE_SLOW_PICK)                 // fault injection: widen the pick/reserve window
             for (int i = 0; i < 8; ++i) __builtin_amdgcn_s_sleep(127);
