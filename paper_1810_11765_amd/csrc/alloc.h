@@ -33,22 +33,32 @@ namespace smmo {
 constexpr uint32_t kOomRounds = 4096;
 constexpr uint32_t kAllocIters = 1u << 18;
 
-// initialize_block<T> (Alg. 8): type first, then (after a release) the words.
-// The iteration word is zeroed as well, so a block re-initialized during a
-// do-all is never visited by it.
+// initialize_block<T> (Alg. 8): type and iteration word first, then, once
+// both stores have completed, the allocation word.  A reservation that sees
+// the new word therefore reads the new type (see alloc_piece).  The zeroed
+// iteration word keeps a block re-initialized during a do-all out of it.
+// No plain store of this wave needs to be visible before the word: a new
+// object's fields are written after its reservation, and no method reads
+// fields written in the same do-all (phases are separate kernels, each
+// ending with a release).
 // With `word` the allocation word starts as given instead of the padding
 // (all ones: a block whose every slot goes to the caller).
 __device__ inline void initialize_block(const DevHeap& h, uint32_t cls, uint64_t bid, uint64_t word) {
     at_store32(&h.type[bid], cls);
     at_store(&h.iter[bid], 0);
-    at_store_rel(&h.alloc[bid], word);
+    at_store_ordered(&h.alloc[bid], word);
 }
 
 // invalidate(bid) (Alg. 9, iterative).  True if this call took the block
 // from "empty" to "invalidated"; the caller then frees it.
+// The OR is relaxed: every word it races with is an agent-scope atomic, and
+// the type is read with a device-scope load after the OR has returned.  No
+// plain store into the block's data can be pending in this do-all, since a
+// method writes no field of an object destroyed in the same do-all, and
+// earlier do-alls are separate kernels.
 __device__ inline bool invalidate_block(const DevHeap& h, uint64_t bid) {
     for (uint32_t tries = 0; tries < kSpinLimit; ++tries) {
-        uint64_t before = __hip_atomic_fetch_or(&h.alloc[bid], kOnes, __ATOMIC_ACQ_REL,
+        uint64_t before = __hip_atomic_fetch_or(&h.alloc[bid], kOnes, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
         if (before == kOnes) return false;          // nothing invalidated
         uint32_t t = at_load32(&h.type[bid]);
@@ -147,7 +157,8 @@ __device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t 
         const uint64_t mask = rotl64(lowest_k_bits(rotr64(freeb, rot), want), rot);
         // The type read below must see the type written before the word this
         // OR observed was re-initialized (Alg. 8's fence).  The writer
-        // publishes the word with a release store after the type; here the OR
+        // stores the word only after its type store has completed at the
+        // device coherence point (initialize_block); here the OR
         // has returned before the type load is issued (it depends on `got`
         // through the branch, and the compiler may not move it up), and the
         // type load is a device-scope load, so it reads at the device

@@ -72,8 +72,23 @@ __device__ inline uint32_t at_load32(const uint32_t* p) {
 __device__ inline void at_store(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void at_store_rel(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Wait until every memory operation this wave has issued has completed.  An
+// agent-scope store is complete once it has reached the device coherence
+// point, so agent-scope accesses issued after the wait, from any XCD, are
+// ordered after it.  This is the ordering Alg. 8's fence provides between a
+// block's type and its allocation word.  A C++ release store would add a
+// write-back of this XCD's whole L2, which only plain stores need; the words
+// it orders here are all agent-scope atomics.  (vmcnt(0); the expcnt and
+// lgkmcnt fields are left at their maximum, i.e. not waited on.)
+__device__ inline void wait_mem_complete() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);      // no compiler motion across the wait
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// Agent-scope store ordered after this wave's earlier agent-scope accesses.
+__device__ inline void at_store_ordered(uint64_t* p, uint64_t v) {
+    wait_mem_complete();
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void at_store32(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

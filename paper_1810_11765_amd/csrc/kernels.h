@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_new_fill(DevHeap h, uint32_t 
         const uint64_t live = cnt == 64 ? kOnes : ((1ull << cnt) - 1);
         at_store32(&h.type[bid], cls);
         at_store(&h.iter[bid], 0);
-        at_store_rel(&h.alloc[bid], h.cls_pad[cls] | live);
+        at_store_ordered(&h.alloc[bid], h.cls_pad[cls] | live);
         bm_clear(h, bm_free(), bid);
         bm_set(h, bm_allocated(cls), bid);
         if (cnt < N) bm_set(h, bm_active(h, cls), bid);
