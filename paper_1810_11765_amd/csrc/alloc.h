@@ -4,14 +4,15 @@
 // The paper coalesces the allocation requests of a warp into one leader
 // thread (Sec. 4.2, after XMalloc).  Here the unit is the 64-lane wavefront:
 //   * one ballot collects the requesting lanes of a class,
-//   * the leader lane reserves as many slots as it can in one block with a
-//     single 64-bit atomic OR (the block's allocation word holds all 64 slots,
-//     one per lane) and moves on to further blocks for the rest,
+//   * the wave reserves as many slots as it can in one block with a single
+//     64-bit atomic OR (the block's allocation word holds all 64 slots, one
+//     per lane) and moves on to further blocks for the rest,
 //   * every lane takes its slot as the n-th set bit of the reserved mask,
 //     n = its rank among the requesting lanes (mbcnt).
 // Destruction groups the lanes of a wave by block and frees each group with
-// one atomic AND.  All bitmap work runs on the leader lane only, so no spin
-// ever waits on a lane of the same wave.
+// one atomic AND.  The bookkeeping runs wave-uniform (dev.h): every atomic
+// once per wave, the bit manipulation on the scalar unit, and no spin ever
+// waits on a lane of the same wave.
 //
 // Slots >= capacity N_T stay set for the life of a block (App. A.1); the
 // capacity-64 rules of Alg. 6/7/9 are applied to the word itself:
@@ -44,9 +45,11 @@ constexpr uint32_t kAllocIters = 1u << 18;
 // With `word` the allocation word starts as given instead of the padding
 // (all ones: a block whose every slot goes to the caller).
 __device__ inline void initialize_block(const DevHeap& h, uint32_t cls, uint64_t bid, uint64_t word) {
-    at_store32(&h.type[bid], cls);
-    at_store(&h.iter[bid], 0);
-    at_store_ordered(&h.alloc[bid], word);
+    if (is_first_lane()) {
+        at_store32(&h.type[bid], cls);
+        at_store(&h.iter[bid], 0);
+        at_store_ordered(&h.alloc[bid], word);
+    }
 }
 
 // invalidate(bid) (Alg. 9, iterative).  True if this call took the block
@@ -57,89 +60,95 @@ __device__ inline void initialize_block(const DevHeap& h, uint32_t cls, uint64_t
 // method writes no field of an object destroyed in the same do-all, and
 // earlier do-alls are separate kernels.
 __device__ inline bool invalidate_block(const DevHeap& h, uint64_t bid) {
+    bid = uni64(bid);
     for (uint32_t tries = 0; tries < kSpinLimit; ++tries) {
-        uint64_t before = __hip_atomic_fetch_or(&h.alloc[bid], kOnes, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t before = w_or(&h.alloc[bid], kOnes);
         if (before == kOnes) return false;          // nothing invalidated
-        uint32_t t = at_load32(&h.type[bid]);
-        if (t >= h.ncls) { set_status(h, SMMO_STATUS_CORRUPT); return false; }
+        const uint32_t t = w_load32(&h.type[bid]);
+        if (t >= h.ncls) { w_set_status(h, SMMO_STATUS_CORRUPT); return false; }
         const uint64_t pad = h.cls_pad[t];
         if (before == pad) return true;             // every slot was free
-        count(h, SMMO_CNT_INVAL_ROLLBACK);
+        w_count(h, SMMO_CNT_INVAL_ROLLBACK);
         // roll back exactly the bits this call set (the zeros of `before`)
-        uint64_t before_rb = at_and(&h.alloc[bid], before);
+        const uint64_t before_rb = w_and(&h.alloc[bid], before);
         // a thread that freed a slot in between saw a full block (FIRST) and
         // waits to set active[t]; perform the deferred deactivation for it
         if (before_rb != kOnes) bm_clear(h, bm_active(h, t), bid);
         if ((before_rb & before) != pad) return false;
         // emptied again while invalidated: try once more
     }
-    guard_hit(h, SMMO_CNT_GUARD_INVAL, SMMO_STATUS_RETRY);
+    w_guard_hit(h, SMMO_CNT_GUARD_INVAL, SMMO_STATUS_RETRY);
     return false;
 }
 
 // Block::deallocate for a mask of slots of class-T objects, then Alg. 2's
-// block state update.  Leader lane only.
+// block state update.
 __device__ inline void dealloc_mask(const DevHeap& h, uint32_t T, uint64_t bid, uint64_t mask) {
-    uint64_t before = at_and(&h.alloc[bid], ~mask);
-    if ((before & mask) != mask) set_status(h, SMMO_STATUS_CORRUPT);   // double free
+    T = uni32(T);
+    bid = uni64(bid);
+    mask = uni64(mask);
+    const uint64_t before = w_and(&h.alloc[bid], ~mask);
+    if ((before & mask) != mask) w_set_status(h, SMMO_STATUS_CORRUPT);   // double free
     const bool first = before == kOnes;
     const bool empty = (before & ~mask) == h.cls_pad[T];
     if (first) bm_set(h, bm_active(h, T), bid);
     if (empty && invalidate_block(h, bid)) {
-        uint32_t t = at_load32(&h.type[bid]);
+        const uint32_t t = w_load32(&h.type[bid]);
         bm_clear(h, bm_active(h, t), bid);
         bm_clear(h, bm_allocated(t), bid);
         bm_set(h, bm_free(), bid);
-        count(h, SMMO_CNT_BLOCK_FREE);
+        w_count(h, SMMO_CNT_BLOCK_FREE);
     }
 }
 
-// One piece of a coalesced allocation (Alg. 1 + Alg. 6), leader lane only:
-// find an active block of class `cls` (r lookups, then the slow path), and
-// reserve up to `want` free slots of it with one atomic OR.  Returns the
-// reserved mask (never 0) and the block in bid_out; returns 0 on OOM.
-__device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t want, uint64_t& seed,
+// One piece of a coalesced allocation (Alg. 1 + Alg. 6), wave-uniform: find
+// an active block of class `cls` (r lookups, then the slow path), and reserve
+// up to `want` free slots of it with one atomic OR.  Returns the reserved
+// mask (never 0) and the block in bid_out; returns 0 on OOM.
+__device__ __forceinline__ uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t want, uint64_t& seed,
                                        uint64_t& bid_out) {
+    cls = uni32(cls);
+    want = uni32(want);
+    seed = uni64(seed);
     uint32_t empty_rounds = 0;
     const bool rotate = !(h.tune & SMMO_TUNE_NO_ROTATE);
     if (h.tune & SMMO_TUNE_NO_COALESCE) want = 1;
+    const bool whole = want >= h.cls_cap[cls];
     for (uint32_t iters = 0;; ++iters) {
         if (iters > kAllocIters) {                        // livelock guard: never hang a kernel
-            guard_hit(h, SMMO_CNT_GUARD_ALLOC, SMMO_STATUS_RETRY);
+            w_guard_hit(h, SMMO_CNT_GUARD_ALLOC, SMMO_STATUS_RETRY);
             return 0;
         }
-        if (iters >= 64 && (iters & 63) == 0 && status_has(h, SMMO_STATUS_RETRY)) return 0;
+        if (iters >= 64 && (iters & 63) == 0 && w_status_has(h, SMMO_STATUS_RETRY)) return 0;
         uint64_t bid = kFail;
         for (uint32_t a = 0; a < h.lookups; ++a) {
             seed = splitmix64(seed);
             bid = bm_try_find_set(h, bm_active(h, cls), seed);
             if (bid != kFail) break;
-            count(h, SMMO_CNT_FIND_FAIL);
+            w_count(h, SMMO_CNT_FIND_FAIL);
             // a request for a whole block or more fills a fresh block by
             // itself, so retrying the lookup cannot save a block: one miss
             // sends it to the slow path
-            if (want >= h.cls_cap[cls]) break;
+            if (whole) break;
         }
         if (bid == kFail) {                               // slow path
             bid = bm_clear_any(h, bm_free(), seed);
             if (bid == kFail) {
-                if (++empty_rounds > kOomRounds || (empty_rounds > 2 && status_has(h, SMMO_STATUS_OOM))) {
-                    guard_hit(h, SMMO_CNT_OOM, SMMO_STATUS_OOM);
+                if (++empty_rounds > kOomRounds || (empty_rounds > 2 && w_status_has(h, SMMO_STATUS_OOM))) {
+                    w_guard_hit(h, SMMO_CNT_OOM, SMMO_STATUS_OOM);
                     return 0;
                 }
                 backoff();
                 continue;
             }
-            count(h, SMMO_CNT_BLOCK_INIT);
-            if (want >= h.cls_cap[cls]) {
+            w_count(h, SMMO_CNT_BLOCK_INIT);
+            if (whole) {
                 // the whole block goes to this request: it starts full and
                 // never becomes active (no other wave can find it before
                 // allocated[cls] lists it, and by then it is full), which
                 // saves the reservation and two active-bitmap updates
                 initialize_block(h, cls, bid, kOnes);
                 bm_set(h, bm_allocated(cls), bid);
-                empty_rounds = 0;
                 bid_out = bid;
                 return ~h.cls_pad[cls];
             }
@@ -150,64 +159,60 @@ __device__ inline uint64_t alloc_piece(const DevHeap& h, uint32_t cls, uint32_t 
         if (h.tune & SMMO_TUNE_SLOW_PICK)                 // fault injection: widen the pick/reserve window
             for (int i = 0; i < 8; ++i) __builtin_amdgcn_s_sleep(127);
         // Block::reserve, coalesced: take up to `want` zero bits, rotated start
-        uint64_t freeb = ~at_load(&h.alloc[bid]);
-        if (!freeb) { count(h, SMMO_CNT_RESERVE_FAIL); continue; }
+        const uint64_t freeb = ~w_load(&h.alloc[bid]);
+        if (!freeb) { w_count(h, SMMO_CNT_RESERVE_FAIL); continue; }
         seed = splitmix64(seed);
         const uint32_t rot = rotate ? (uint32_t)seed & 63 : 0;
         const uint64_t mask = rotl64(lowest_k_bits(rotr64(freeb, rot), want), rot);
         // The type read below must see the type written before the word this
         // OR observed was re-initialized (Alg. 8's fence).  The writer
         // stores the word only after its type store has completed at the
-        // device coherence point (initialize_block); here the OR
-        // has returned before the type load is issued (it depends on `got`
-        // through the branch, and the compiler may not move it up), and the
+        // device coherence point (initialize_block); here the OR has
+        // returned before the type load is issued (its address is uniform
+        // and the load follows the broadcast of the OR's result), and the
         // type load is a device-scope load, so it reads at the device
         // coherence point, where the type already is.  An acquire on the OR
         // would also invalidate this CU's caches on every reservation, which
         // more than doubled the allocating do-alls' time on MI355X.
-        uint64_t before = at_or(&h.alloc[bid], mask);
+        const uint64_t before = w_or(&h.alloc[bid], mask);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        count(h, SMMO_CNT_RESERVE_ATOMIC);
+        w_count(h, SMMO_CNT_RESERVE_ATOMIC);
         const uint64_t got = mask & ~before;
-        if (!got) { count(h, SMMO_CNT_RESERVE_FAIL); continue; }
-        uint32_t t = at_load32(&h.type[bid]);
-        if (t >= h.ncls) { set_status(h, SMMO_STATUS_CORRUPT); continue; }
+        if (!got) { w_count(h, SMMO_CNT_RESERVE_FAIL); continue; }
+        const uint32_t t = w_load32(&h.type[bid]);
+        if (t >= h.ncls) { w_set_status(h, SMMO_STATUS_CORRUPT); continue; }
         if ((before | got) == kOnes) bm_clear(h, bm_active(h, t), bid);   // this call filled it
         if (t != cls) {                                   // block changed type: roll back
-            count(h, SMMO_CNT_TYPE_ROLLBACK);
+            w_count(h, SMMO_CNT_TYPE_ROLLBACK);
             dealloc_mask(h, t, bid, got);
             continue;
         }
-        empty_rounds = 0;
         bid_out = bid;
         return got;
     }
 }
 
-// Wave-collective allocation: every lane of the wave must call this with the
-// same `cls`; lanes with want=true receive a handle (0 on OOM).
-__device__ inline uint64_t wave_alloc(const DevHeap& h, uint32_t cls, bool want, uint64_t wave_seed) {
+// Wave-collective allocation: every active lane of the wave must call this
+// with the same `cls` and `wave_seed`; lanes with want=true receive a handle
+// (0 on OOM).
+__device__ __forceinline__ uint64_t wave_alloc(const DevHeap& h, uint32_t cls, bool want, uint64_t wave_seed) {
     const uint64_t req = ballot(want);
     if (!req) return 0;
-    const uint32_t lane = lane_id();
-    const uint32_t leader = ctz64(req);
     const uint32_t k = popc64(req);
     const uint32_t rank = lanes_below(req);
-    uint64_t seed = wave_seed;
+    uint64_t seed = uni64(wave_seed);
     uint64_t mine = 0;
     uint32_t taken = 0;
     while (taken < k) {                       // wave-uniform loop
-        uint64_t got = 0, bid = 0;
-        if (lane == leader) got = alloc_piece(h, cls, k - taken, seed, bid);
-        got = readlane64(got, leader);
-        bid = readlane64(bid, leader);
+        uint64_t bid = 0;
+        const uint64_t got = alloc_piece(h, cls, k - taken, seed, bid);
         if (!got) break;                      // OOM: remaining lanes get null
         const uint32_t n = popc64(got);
         if (want && rank >= taken && rank < taken + n)
             mine = make_ref(cls, bid, nth_set_bit(got, rank - taken));
         taken += n;
     }
-    if (lane == leader) count(h, SMMO_CNT_ALLOC_OBJ, taken);
+    w_count(h, SMMO_CNT_ALLOC_OBJ, taken);
     return mine;
 }
 
@@ -222,10 +227,8 @@ __device__ inline void wave_destroy(const DevHeap& h, uint64_t ref, bool want) {
         const bool in = ((pending >> lane) & 1) && ref_block(ref) == ref_block(lref);
         const uint64_t grp = ballot(in);
         const uint64_t mask = wave_or(in ? (1ull << ref_slot(ref)) : 0ull);
-        if (lane == leader) {
-            dealloc_mask(h, ref_cls(lref), ref_block(lref), mask);
-            count(h, SMMO_CNT_FREE_OBJ, popc64(grp));
-        }
+        dealloc_mask(h, ref_cls(lref), ref_block(lref), mask);
+        w_count(h, SMMO_CNT_FREE_OBJ, popc64(grp));
         pending &= ~grp;
     }
 }
@@ -235,10 +238,8 @@ __device__ inline void wave_destroy(const DevHeap& h, uint64_t ref, bool want) {
 __device__ inline void wave_destroy_self(const DevHeap& h, uint32_t cls, uint64_t bid, bool want) {
     const uint64_t mask = ballot(want);
     if (!mask) return;
-    if (lane_id() == ctz64(mask)) {
-        dealloc_mask(h, cls, bid, mask);
-        count(h, SMMO_CNT_FREE_OBJ, popc64(mask));
-    }
+    dealloc_mask(h, cls, bid, mask);
+    w_count(h, SMMO_CNT_FREE_OBJ, popc64(mask));
 }
 
 }  // namespace smmo

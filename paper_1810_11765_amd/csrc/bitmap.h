@@ -6,10 +6,13 @@
 // the first bit or clears the last bit of a container is responsible for the
 // parent bit and updates it with the spinning (non-try) form (Sec. 4.1.3).
 //
-// On gfx950 these functions are executed by ONE lane of a wave (the wave's
-// leader); a spin here never waits on another lane of its own wave, which a
-// wave64 could not schedule (lanes of a wave share one program counter).
-// Every spin is bounded: past kSpinLimit it raises SMMO_STATUS_RETRY and gives
+// On gfx950 these functions run wave-uniform (dev.h): the whole wave, or a
+// single lane of it, executes them on values that are the same in every
+// active lane, and each atomic is performed once.  So a spin never waits on
+// another lane of its own wave, which a wave64 could not schedule (lanes of
+// a wave share one program counter), and the bit manipulation runs on the
+// scalar unit.  Arguments are made uniform on entry (the first active lane's
+// value).  Every spin is bounded: past kSpinLimit it raises SMMO_STATUS_RETRY and gives
 // up, so a kernel always terminates even on a corrupted heap; once the status
 // word holds RETRY (the run is already invalid) spins give up early, so the
 // kernel ends soon after the first bound is hit.
@@ -28,17 +31,19 @@ __device__ inline uint64_t* bm_word(const DevHeap& h, uint32_t b, uint32_t level
 // set(pos) from `level` upwards: switch the bit 0 -> 1, retrying while it is
 // still 1 (a pending clear of another wave); a set-first continues one level up.
 __device__ inline void bm_set_from(const DevHeap& h, uint32_t b, uint32_t level, uint64_t pos) {
-    for (uint32_t l = level; l < h.nlevels; ++l) {
+    b = uni32(b);
+    pos = uni64(pos);
+    for (uint32_t l = uni32(level); l < h.nlevels; ++l) {
         uint64_t* w = bm_word(h, b, l, pos >> 6);
         const uint64_t bit = 1ull << (pos & 63);
-        uint64_t prev = at_or(w, bit);
+        uint64_t prev = w_or(w, bit);
         uint32_t spins = 0;
         while (prev & bit) {
-            if (++spins > kSpinLimit) { guard_hit(h, SMMO_CNT_GUARD_SPIN, SMMO_STATUS_RETRY); return; }
-            if ((spins & 255) == 0 && status_has(h, SMMO_STATUS_RETRY)) return;
-            count(h, SMMO_CNT_SPIN);
+            if (++spins > kSpinLimit) { w_guard_hit(h, SMMO_CNT_GUARD_SPIN, SMMO_STATUS_RETRY); return; }
+            if ((spins & 255) == 0 && w_status_has(h, SMMO_STATUS_RETRY)) return;
+            w_count(h, SMMO_CNT_SPIN);
             backoff();
-            prev = at_or(w, bit);
+            prev = w_or(w, bit);
         }
         if (prev != 0) return;          // not the first bit of the container
         pos >>= 6;
@@ -47,17 +52,19 @@ __device__ inline void bm_set_from(const DevHeap& h, uint32_t b, uint32_t level,
 
 // clear(pos) from `level` upwards (spinning form).
 __device__ inline void bm_clear_from(const DevHeap& h, uint32_t b, uint32_t level, uint64_t pos) {
-    for (uint32_t l = level; l < h.nlevels; ++l) {
+    b = uni32(b);
+    pos = uni64(pos);
+    for (uint32_t l = uni32(level); l < h.nlevels; ++l) {
         uint64_t* w = bm_word(h, b, l, pos >> 6);
         const uint64_t bit = 1ull << (pos & 63);
-        uint64_t prev = at_and(w, ~bit);
+        uint64_t prev = w_and(w, ~bit);
         uint32_t spins = 0;
         while (!(prev & bit)) {
-            if (++spins > kSpinLimit) { guard_hit(h, SMMO_CNT_GUARD_SPIN, SMMO_STATUS_RETRY); return; }
-            if ((spins & 255) == 0 && status_has(h, SMMO_STATUS_RETRY)) return;
-            count(h, SMMO_CNT_SPIN);
+            if (++spins > kSpinLimit) { w_guard_hit(h, SMMO_CNT_GUARD_SPIN, SMMO_STATUS_RETRY); return; }
+            if ((spins & 255) == 0 && w_status_has(h, SMMO_STATUS_RETRY)) return;
+            w_count(h, SMMO_CNT_SPIN);
             backoff();
-            prev = at_and(w, ~bit);
+            prev = w_and(w, ~bit);
         }
         if (prev != bit) return;        // container still has other bits (popc(prev) > 1)
         pos >>= 6;
@@ -69,9 +76,11 @@ __device__ inline void bm_clear(const DevHeap& h, uint32_t b, uint64_t pos) { bm
 
 // try_clear(pos) (Alg. 3): one atomic AND; true if this call cleared the bit.
 __device__ inline bool bm_try_clear(const DevHeap& h, uint32_t b, uint64_t pos) {
+    b = uni32(b);
+    pos = uni64(pos);
     uint64_t* w = bm_word(h, b, 0, pos >> 6);
     const uint64_t bit = 1ull << (pos & 63);
-    uint64_t prev = at_and(w, ~bit);
+    const uint64_t prev = w_and(w, ~bit);
     if (!(prev & bit)) return false;
     if (prev == bit && h.nlevels > 1) bm_clear_from(h, b, 1, pos >> 6);
     return true;
@@ -86,14 +95,17 @@ __device__ inline uint32_t rot_ffs(uint64_t w, uint32_t rot) {
 // try_find_set() (Alg. 4), top-down from the single top word.  `seed` gives a
 // different rotation per level; it depends on the wave and changes per retry.
 __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_t seed) {
-    if ((h.tune & SMMO_TUNE_FORCE_FAIL) && (uint32_t)(splitmix64(seed) % 1000000u) < h.force_fail_ppm)
-        return kFail;
+    b = uni32(b);
+    seed = uni64(seed);
+    if (h.tune & SMMO_TUNE_FORCE_FAIL) {
+        if ((uint32_t)(splitmix64(seed) % 1000000u) < h.force_fail_ppm) return kFail;
+    }
     const bool rotate = !(h.tune & SMMO_TUNE_NO_ROTATE);
     uint64_t idx = 0;
     for (int l = (int)h.nlevels - 1; l >= 0; --l) {
-        uint64_t w = at_load(bm_word(h, b, (uint32_t)l, idx));
+        const uint64_t w = w_load(bm_word(h, b, (uint32_t)l, idx));
         if (!w) return kFail;
-        uint32_t bit = rotate ? rot_ffs(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
+        const uint32_t bit = rotate ? rot_ffs(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
         idx = (idx << 6) | bit;
     }
     return idx;
@@ -101,9 +113,10 @@ __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_
 
 // clear(): find and clear any set bit; kFail if a lookup finds none.
 __device__ inline uint64_t bm_clear_any(const DevHeap& h, uint32_t b, uint64_t& seed) {
+    seed = uni64(seed);
     for (uint32_t tries = 0; tries < 64; ++tries) {
         seed = splitmix64(seed);
-        uint64_t i = bm_try_find_set(h, b, seed);
+        const uint64_t i = bm_try_find_set(h, b, seed);
         if (i == kFail) return kFail;
         if (bm_try_clear(h, b, i)) return i;
     }

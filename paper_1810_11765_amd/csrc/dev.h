@@ -168,6 +168,45 @@ __device__ inline uint64_t lowest_k_bits(uint64_t v, uint32_t k) {
     return v & ((1ull << p) - 1);
 }
 
+// -------------------------------------------------- wave-uniform ops ----
+// The allocator's bookkeeping (bitmap searches, block words) runs on the
+// whole wave with wave-uniform values: the compiler keeps them in scalar
+// registers and works on them with the scalar unit's 64-bit instructions,
+// instead of spending a full vector instruction per step on one lane.  A
+// heap word is read by every active lane at the same address (a single
+// memory request) and broadcast; an atomic is performed once, by the first
+// active lane.  These functions are also correct with one active lane.
+__device__ inline uint32_t first_lane() { return ctz64(__builtin_amdgcn_read_exec()); }
+__device__ inline bool is_first_lane() { return lane_id() == first_lane(); }
+// the first active lane's value, as a wave-uniform value
+__device__ inline uint32_t uni32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ inline uint64_t uni64(uint64_t v) {
+    const uint32_t lo = uni32((uint32_t)v), hi = uni32((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t w_load(const uint64_t* p) { return uni64(at_load(p)); }
+__device__ inline uint32_t w_load32(const uint32_t* p) { return uni32(at_load32(p)); }
+__device__ inline uint64_t w_or(uint64_t* p, uint64_t v) {
+    uint64_t r = 0;
+    if (is_first_lane()) r = at_or(p, v);
+    return uni64(r);
+}
+__device__ inline uint64_t w_and(uint64_t* p, uint64_t v) {
+    uint64_t r = 0;
+    if (is_first_lane()) r = at_and(p, v);
+    return uni64(r);
+}
+__device__ inline void w_set_status(const DevHeap& h, uint32_t bits) {
+    if (is_first_lane()) set_status(h, bits);
+}
+__device__ inline void w_count(const DevHeap& h, uint32_t which, uint64_t n = 1) {
+    if ((h.tune & SMMO_TUNE_STATS) && is_first_lane()) count(h, which, n);
+}
+__device__ inline void w_guard_hit(const DevHeap& h, uint32_t which, uint32_t bits) {
+    if (is_first_lane()) guard_hit(h, which, bits);
+}
+__device__ inline bool w_status_has(const DevHeap& h, uint32_t bits) { return (w_load32(h.status) & bits) != 0; }
+
 // ------------------------------------------------------------------ RNG ----
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): first output for seed x.
 __host__ __device__ inline uint64_t splitmix64(uint64_t x) {

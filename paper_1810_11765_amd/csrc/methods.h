@@ -21,7 +21,7 @@ struct MAxpy {
     __device__ static Prep prepare(const DevHeap& h, uint32_t cls, const Args& a) {
         return {h.hdr->field_off[cls][a.fx], h.hdr->field_off[cls][a.fy]};
     }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         if (o.live) {
             float& y = o.at<float>(p.oy);
             const float ax = a.a * o.at<float>(p.ox);
@@ -110,7 +110,7 @@ struct MDestroyAll {
     static constexpr bool kSnapshot = false;
     struct Prep {};
     __device__ static Prep prepare(const DevHeap&, uint32_t, const Args&) { return {}; }
-    __device__ static void run(const Obj& o, const Prep&, const Args&) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep&, const Args&) {
         wave_destroy_self(o.h, o.cls, o.bid, o.live);
     }
 };
@@ -123,7 +123,7 @@ struct MVisit {
     __device__ static Prep prepare(const DevHeap& h, uint32_t cls, const Args&) {
         return {h.hdr->field_off[cls][0]};
     }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         if (o.live) atomicAdd(&a.visits[o.at<int32_t>(p.oid)], 1u);
     }
 };
@@ -137,7 +137,7 @@ struct MChurn {
     __device__ static Prep prepare(const DevHeap& h, uint32_t cls, const Args&) {
         return {h.hdr->field_off[cls][0], h.hdr->field_off[cls][1], h.hdr->field_off[cls][2]};
     }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         bool die = false;
         int32_t nid = 0;
         if (o.live) {
@@ -178,7 +178,7 @@ struct MMix {
             for (uint32_t k = 0; k < h.hdr->field_bytes[c][f]; ++k) q[k] = 0;
         }
     }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         bool die = false, to_b = false;
         int32_t nid = 0;
         if (o.live) {
@@ -207,7 +207,7 @@ struct MStress {
     static constexpr bool kSnapshot = false;
     struct Prep { uint32_t unused; };
     __device__ static Prep prepare(const DevHeap&, uint32_t, const Args&) { return {0}; }
-    __device__ static void run(const Obj& o, const Prep&, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep&, const Args& a) {
         const uint32_t key = (uint32_t)(o.bid * 64 + o.lane);
         for (uint32_t k = 0; k < a.iters; ++k) {
             const bool act = o.live && o.lane < a.lanes;
@@ -238,7 +238,7 @@ struct MLifePlan {
     static constexpr bool kSnapshot = false;
     using Prep = LifePrep;
     __device__ static Prep prepare(const DevHeap& h, uint32_t, const Args& a) { return life_prep(h, a); }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         if (!o.live) return;
         const int32_t x = o.at<int32_t>(p.cx), y = o.at<int32_t>(p.cy);
         const int32_t W = a.width, H = a.height;
@@ -266,7 +266,7 @@ struct MLifeAgent {
     static constexpr bool kSnapshot = false;
     using Prep = LifePrep;
     __device__ static Prep prepare(const DevHeap& h, uint32_t, const Args& a) { return life_prep(h, a); }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         bool die = false;
         if (o.live) {
             const int32_t c = o.at<int32_t>(p.gc);
@@ -283,7 +283,7 @@ struct MLifeCommit {
     static constexpr bool kSnapshot = false;    // creates Agents, enumerates Cells
     using Prep = LifePrep;
     __device__ static Prep prepare(const DevHeap& h, uint32_t, const Args& a) { return life_prep(h, a); }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         bool born = false;
         int32_t c = 0;
         if (o.live) {
@@ -327,7 +327,7 @@ struct MFishPlan {
     static constexpr bool kSnapshot = false;
     using Prep = WatorPrep;
     __device__ static Prep prepare(const DevHeap& h, uint32_t, const Args& a) { return wator_prep(h, a); }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         if (!o.live) return;
         const int32_t pos = o.at<int32_t>(p.fp);
         o.at<int32_t>(p.fa) += 1;
@@ -353,7 +353,7 @@ struct MFishMove {
     static constexpr bool kSnapshot = true;     // creates Fish
     using Prep = WatorPrep;
     __device__ static Prep prepare(const DevHeap& h, uint32_t, const Args& a) { return wator_prep(h, a); }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         bool win = false, breed = false;
         int32_t pos = 0, t = -1;
         if (o.live) {
@@ -387,7 +387,7 @@ struct MSharkPlan {
     static constexpr bool kSnapshot = false;
     using Prep = WatorPrep;
     __device__ static Prep prepare(const DevHeap& h, uint32_t, const Args& a) { return wator_prep(h, a); }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         if (!o.live) return;
         const int32_t pos = o.at<int32_t>(p.sp);
         o.at<int32_t>(p.sa) += 1;
@@ -417,7 +417,7 @@ struct MSharkMove {
     static constexpr bool kSnapshot = true;     // creates Sharks
     using Prep = WatorPrep;
     __device__ static Prep prepare(const DevHeap& h, uint32_t, const Args& a) { return wator_prep(h, a); }
-    __device__ static void run(const Obj& o, const Prep& p, const Args& a) {
+    __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
         bool win = false, breed = false, starve = false;
         int32_t pos = 0, t = -1, age = 0, energy = 0;
         uint64_t prey = 0;
