@@ -426,13 +426,18 @@ ABLATION_VARIANTS = [("default", 0, 5), ("noshift", 1, 5), ("nocoal", 2, 5), ("n
                      ("r1", 0, 1), ("r2", 0, 2), ("r3", 0, 3), ("r5", 0, 5), ("r8", 0, 8)]
 
 
+ABLATION_BLOCKS = 65536
+
+
 def ablation_suite(torch, workloads, steps):
-    """Predator-prey 1024 x 1024 (seed 42, 32,768-block heap) under each
-    allocator variant of Sec. 6.3: rotation off (noshift), request
-    coalescing off (nocoal), both, and r = 1..8 active-block lookups.  Per
-    variant: step time (events around each step), fragmentation F every 10
-    steps (occupancy query, outside the timed spans) and whether the final
-    state equals the oracle's."""
+    """Predator-prey 1024 x 1024 (seed 42) under each allocator variant of
+    Sec. 6.3: rotation off (noshift), request coalescing off (nocoal), both,
+    and r = 1..8 active-block lookups.  Per variant: step time (events around
+    each step), fragmentation F every 10 steps (occupancy query, outside the
+    timed spans) and whether the final state equals the oracle's.  The heap
+    has 65,536 blocks, twice the workload's own: without rotation F reaches
+    about 0.86 during the population peak, which would exhaust 32,768 blocks
+    and turn the comparison into one of out-of-memory handling."""
     from oracle import core
     from paper_1810_11765_amd import smmo as S
     seed, side = 42, 1024
@@ -440,7 +445,7 @@ def ablation_suite(torch, workloads, steps):
     out = {}
     for name, flags, lookups in ABLATION_VARIANTS:
         _progress("ablation", name)
-        w = workloads.WaTor(seed=seed, width=side, height=side, kind0=kind0)
+        w = workloads.WaTor(seed=seed, width=side, height=side, kind0=kind0, num_blocks=ABLATION_BLOCKS)
         kind0 = w.kind0
         w.heap.set_tuning(flags, lookups, 0)
         w.populate()
@@ -464,7 +469,7 @@ def ablation_suite(torch, workloads, steps):
         w = out[name].pop("_w")
         out[name]["identical_to_oracle"] = _wator_same(w, ref)
         w.heap.close()
-    return {"workload": f"predator-prey {side}x{side} torus, seed {seed}, 32768-block heap, {steps} steps",
+    return {"workload": f"predator-prey {side}x{side} torus, seed {seed}, {ABLATION_BLOCKS}-block heap, {steps} steps",
             "variants": out}
 
 

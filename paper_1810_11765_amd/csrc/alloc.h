@@ -27,10 +27,11 @@
 namespace smmo {
 
 // Bounds of the allocator's retry loops.  A wave gives up an allocation
-// after kOomRounds consecutive rounds that find neither an active nor a free
-// block (OOM), or after kAllocIters iterations in all (RETRY: a livelock
-// guard that contention alone does not reach).  Once the status word holds
-// OOM or RETRY, later requests give up after a few rounds instead.
+// after kOomRounds rounds that find neither an active block nor any free
+// block (the free bitmap's top word empty: OOM), or after kAllocIters
+// iterations in all (RETRY: a livelock guard that contention alone does not
+// reach).  Once the status word holds OOM or RETRY, later requests give up
+// after a few rounds instead.
 constexpr uint32_t kOomRounds = 4096;
 constexpr uint32_t kAllocIters = 1u << 18;
 
@@ -134,7 +135,11 @@ __device__ __forceinline__ uint64_t alloc_piece(const DevHeap& h, uint32_t cls, 
         if (bid == kFail) {                               // slow path
             bid = bm_clear_any(h, bm_free(), seed);
             if (bid == kFail) {
-                if (++empty_rounds > kOomRounds || (empty_rounds > 2 && w_status_has(h, SMMO_STATUS_OOM))) {
+                // only a round that finds the free bitmap empty counts
+                // towards OOM; a miss caused by contention is retried (up
+                // to the livelock guard above)
+                if (bm_top_empty(h, bm_free()) &&
+                    (++empty_rounds > kOomRounds || (empty_rounds > 2 && w_status_has(h, SMMO_STATUS_OOM)))) {
                     w_guard_hit(h, SMMO_CNT_OOM, SMMO_STATUS_OOM);
                     return 0;
                 }

@@ -111,7 +111,8 @@ __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_
     return idx;
 }
 
-// clear(): find and clear any set bit; kFail if a lookup finds none.
+// clear(): find and clear any set bit; kFail if a lookup finds none.  A
+// lost race for the bit found backs off before the next lookup.
 __device__ inline uint64_t bm_clear_any(const DevHeap& h, uint32_t b, uint64_t& seed) {
     seed = uni64(seed);
     for (uint32_t tries = 0; tries < 64; ++tries) {
@@ -119,8 +120,16 @@ __device__ inline uint64_t bm_clear_any(const DevHeap& h, uint32_t b, uint64_t& 
         const uint64_t i = bm_try_find_set(h, b, seed);
         if (i == kFail) return kFail;
         if (bm_try_clear(h, b, i)) return i;
+        backoff();
     }
     return kFail;
+}
+
+// The top word of bitmap b is empty, i.e. no bit is set (up to the sets and
+// clears in flight).  A lookup that fails while the top word still has bits
+// met a stale upper-level bit: contention, not an empty bitmap.
+__device__ inline bool bm_top_empty(const DevHeap& h, uint32_t b) {
+    return w_load(bm_word(h, uni32(b), h.nlevels - 1, 0)) == 0;
 }
 
 }  // namespace smmo
