@@ -276,7 +276,10 @@ typedef struct smmo_stress_args {
 } smmo_stress_args;
 
 /* Life-like grid on a width x height torus.  Cell {int32 x, int32 y, int8
- * alive}: alive bit 0 = current, bit 1 = next.  Agent {int32 cell, int32 age}.
+ * alive}: alive bit 0 = current, bit 1 = next (plan sets bit 1; commit copies
+ * it into bit 0 and leaves bit 1 as it is, so the agent phase, which reads
+ * bit 1, sees the same value before and after the commit of its cell and may
+ * run concurrently with the commit phase).  Agent {int32 cell, int32 age}.
  * cell_ref[c] is the handle of cell c = y*width + x (device array). */
 typedef struct smmo_life_args {
     const uint64_t* cell_ref;
@@ -371,6 +374,30 @@ int smmo_parallel_destroy(smmo_heap* heap, const uint64_t* refs, uint64_t nthrea
  * (<= SMMO_ARGS_MAX bytes). */
 int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
                      uint64_t args_bytes, void* stream);
+
+/* The iteration snapshot of Sec. 3.1 on its own: for `cls` and its
+ * subclasses, record the objects live now (each allocated block's iteration
+ * word <- its allocation word).  With smmo_parallel_do_snapshot this splits a
+ * do-all into "fix the objects to visit" and "visit them", so that another
+ * do-all that creates objects of `cls` can run between the two, or at the
+ * same time as the second on another stream, without its objects being
+ * visited.  Asynchronous on `stream`. */
+int smmo_snapshot(smmo_heap* heap, uint32_t cls, void* stream);
+
+/* smmo_parallel_do over the objects recorded by the last smmo_snapshot of
+ * `cls` (and its subclasses) instead of those live at launch; objects created
+ * since the snapshot are not visited.  Between the snapshot and the end of
+ * this call no recorded object may be destroyed except by this call's own
+ * method (as in any do-all, on itself), and no snapshot of these classes may
+ * be taken.  Every method that smmo_parallel_do runs through the generic
+ * do-all is accepted; SMMO_M_AXPY and the n-body methods give SMMO_EINVAL.
+ * Calls on one heap that run at the same time on different streams share
+ * the heap's block-list buffer: at most one of them may build a block list
+ * (do-alls of heaps with at least list_min_words level-0 words, smmo_launch),
+ * so for concurrent do-alls on such heaps raise list_min_words or set
+ * SMMO_TUNE_FLAT_ENUM. */
+int smmo_parallel_do_snapshot(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
+                              uint64_t args_bytes, void* stream);
 
 /* Live objects of class `cls`.  Synchronizes the stream. */
 int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream);

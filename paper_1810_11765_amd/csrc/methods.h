@@ -278,6 +278,8 @@ struct MLifeAgent {
 };
 
 // Cell::commit: a dead cell that becomes alive creates its Agent; alive <- next.
+// Bit 1 keeps the next state, so Agent::step may run before, after or during
+// this phase and read the same value.
 struct MLifeCommit {
     using Args = smmo_life_args;
     static constexpr bool kSnapshot = false;    // creates Agents, enumerates Cells
@@ -290,7 +292,7 @@ struct MLifeCommit {
             uint8_t& al = o.at<uint8_t>(p.ca);
             const uint8_t v = al;
             born = !(v & 1) && (v & 2);
-            al = (uint8_t)((v >> 1) & 1);
+            al = (uint8_t)((v & 2) ? 3 : 0);     // current <- next; bit 1 (next) stays for the agent phase
             c = o.at<int32_t>(p.cy) * a.width + o.at<int32_t>(p.cx);
         }
         const uint64_t r = wave_alloc(o.h, a.agent_cls, born, o.seed);

@@ -312,12 +312,18 @@ int snapshot_class(smmo_heap* H, uint32_t cls, hipStream_t s) {
 }
 
 template <class M>
-int launch_doall(smmo_heap* H, uint32_t cls, const void* args, uint64_t bytes, hipStream_t s) {
+int launch_doall(smmo_heap* H, uint32_t cls, const void* args, uint64_t bytes, hipStream_t s,
+                 bool from_snapshot = false) {
     typename M::Args a;
     int rc = unpack_args(a, args, bytes, "parallel_do");
     if (rc) return rc;
     uint32_t cl[SMMO_MAX_CLASSES];
     const uint32_t n = subtree(H, cls, cl);
+    if (from_snapshot) {                  // the iteration words of an earlier smmo_snapshot
+        for (uint32_t i = 0; i < n; ++i)
+            if ((rc = launch_doall_one<M, true>(H, cl[i], a, false, s))) return rc;
+        return SMMO_OK;
+    }
     if (n == 1) return launch_doall_one<M, M::kSnapshot>(H, cls, a, M::kSnapshot, s);
     // class and subclasses (Sec. 2.1): one kernel per class, every class's
     // iteration words taken before the first, so no kernel visits objects an
@@ -558,11 +564,13 @@ int smmo_parallel_destroy(smmo_heap* heap, const uint64_t* refs, uint64_t nthrea
     return SMMO_OK;
 }
 
-int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args, uint64_t args_bytes,
-                     void* stream) {
+static int parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args, uint64_t args_bytes,
+                       void* stream, bool from_snapshot) {
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     hipStream_t s = S(stream);
+    if (from_snapshot && (method_id == SMMO_M_AXPY || (method_id >= SMMO_M_NBODY_INSERT && method_id <= SMMO_M_NBODY_MOVE)))
+        return fail(SMMO_EINVAL, "method %u has no snapshot form", method_id);
     switch (method_id) {
         case SMMO_M_AXPY: {
             smmo_axpy_args a;
@@ -587,9 +595,9 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
             }
             return SMMO_OK;
         }
-        case SMMO_M_DESTROY_ALL: return launch_doall<MDestroyAll>(heap, cls, nullptr, 0, s);
-        case SMMO_M_VISIT: return launch_doall<MVisit>(heap, cls, args, args_bytes, s);
-        case SMMO_M_CHURN: return launch_doall<MChurn>(heap, cls, args, args_bytes, s);
+        case SMMO_M_DESTROY_ALL: return launch_doall<MDestroyAll>(heap, cls, nullptr, 0, s, from_snapshot);
+        case SMMO_M_VISIT: return launch_doall<MVisit>(heap, cls, args, args_bytes, s, from_snapshot);
+        case SMMO_M_CHURN: return launch_doall<MChurn>(heap, cls, args, args_bytes, s, from_snapshot);
         case SMMO_M_MIX: {
             smmo_mix_args a;
             rc = unpack_args(a, args, args_bytes, "mix");
@@ -597,7 +605,7 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
             if (a.cls_a >= heap->hdr.ncls || a.cls_b >= heap->hdr.ncls || heap->hdr.field_bytes[a.cls_a][0] != 4 ||
                 heap->hdr.field_bytes[a.cls_b][0] != 4 || heap->hdr.field_bytes[cls][0] != 4)
                 return fail(SMMO_EINVAL, "mix: classes need an int32 field 0");
-            return launch_doall<MMix>(heap, cls, args, args_bytes, s);
+            return launch_doall<MMix>(heap, cls, args, args_bytes, s, from_snapshot);
         }
         case SMMO_M_STRESS: {
             smmo_stress_args a;
@@ -610,15 +618,15 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
             if (!other || heap->hdr.field_bytes[a.cls_a][0] != 4 || heap->hdr.field_bytes[a.cls_b][0] != 4 ||
                 a.lanes > 64)
                 return fail(SMMO_EINVAL, "stress: two classes outside the do-all's with an int32 field 0, lanes <= 64");
-            return launch_doall<MStress>(heap, cls, args, args_bytes, s);
+            return launch_doall<MStress>(heap, cls, args, args_bytes, s, from_snapshot);
         }
-        case SMMO_M_LIFE_PLAN: return launch_doall<MLifePlan>(heap, cls, args, args_bytes, s);
-        case SMMO_M_LIFE_AGENT: return launch_doall<MLifeAgent>(heap, cls, args, args_bytes, s);
-        case SMMO_M_LIFE_COMMIT: return launch_doall<MLifeCommit>(heap, cls, args, args_bytes, s);
-        case SMMO_M_WATOR_FISH_PLAN: return launch_doall<MFishPlan>(heap, cls, args, args_bytes, s);
-        case SMMO_M_WATOR_FISH_MOVE: return launch_doall<MFishMove>(heap, cls, args, args_bytes, s);
-        case SMMO_M_WATOR_SHARK_PLAN: return launch_doall<MSharkPlan>(heap, cls, args, args_bytes, s);
-        case SMMO_M_WATOR_SHARK_MOVE: return launch_doall<MSharkMove>(heap, cls, args, args_bytes, s);
+        case SMMO_M_LIFE_PLAN: return launch_doall<MLifePlan>(heap, cls, args, args_bytes, s, from_snapshot);
+        case SMMO_M_LIFE_AGENT: return launch_doall<MLifeAgent>(heap, cls, args, args_bytes, s, from_snapshot);
+        case SMMO_M_LIFE_COMMIT: return launch_doall<MLifeCommit>(heap, cls, args, args_bytes, s, from_snapshot);
+        case SMMO_M_WATOR_FISH_PLAN: return launch_doall<MFishPlan>(heap, cls, args, args_bytes, s, from_snapshot);
+        case SMMO_M_WATOR_FISH_MOVE: return launch_doall<MFishMove>(heap, cls, args, args_bytes, s, from_snapshot);
+        case SMMO_M_WATOR_SHARK_PLAN: return launch_doall<MSharkPlan>(heap, cls, args, args_bytes, s, from_snapshot);
+        case SMMO_M_WATOR_SHARK_MOVE: return launch_doall<MSharkMove>(heap, cls, args, args_bytes, s, from_snapshot);
         case SMMO_M_NBODY_INSERT:
         case SMMO_M_NBODY_PAIRS:
         case SMMO_M_NBODY_RESOLVE:
@@ -627,6 +635,26 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
         case SMMO_M_NBODY_MOVE: return launch_nbody(heap, cls, method_id, args, args_bytes, s);
         default: return fail(SMMO_EINVAL, "unknown method_id %u", method_id);
     }
+}
+
+int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args, uint64_t args_bytes,
+                     void* stream) {
+    return parallel_do(heap, cls, method_id, args, args_bytes, stream, false);
+}
+
+int smmo_parallel_do_snapshot(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
+                              uint64_t args_bytes, void* stream) {
+    return parallel_do(heap, cls, method_id, args, args_bytes, stream, true);
+}
+
+int smmo_snapshot(smmo_heap* heap, uint32_t cls, void* stream) {
+    int rc = check_heap_cls(heap, cls);
+    if (rc) return rc;
+    uint32_t cl[SMMO_MAX_CLASSES];
+    const uint32_t n = subtree(heap, cls, cl);
+    for (uint32_t i = 0; i < n; ++i)
+        if ((rc = snapshot_class(heap, cl[i], S(stream)))) return rc;
+    return SMMO_OK;
 }
 
 int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream) {

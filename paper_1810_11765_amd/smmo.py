@@ -132,6 +132,8 @@ def lib():
             "smmo_parallel_new": ([P, u32, u64, u32, P, u64, P], i),
             "smmo_parallel_alloc": ([P, u32, u64, u32, u32, P, u64, P], i),
             "smmo_parallel_do": ([P, u32, u32, P, u64, P], i),
+            "smmo_parallel_do_snapshot": ([P, u32, u32, P, u64, P], i),
+            "smmo_snapshot": ([P, u32, P], i),
             "smmo_parallel_destroy": ([P, P, u64, u32, P], i),
             "smmo_occupancy": ([P, P, P, P, P], i),
             "smmo_atomic_probe": ([P, u64, u32, u64, u32, P], i),
@@ -328,9 +330,17 @@ class Heap:
         u, sl, b = list(used), list(slots), list(blocks)
         return {"used": u, "slots": sl, "blocks": b, "F": (1.0 - sum(u) / sum(sl)) if sum(sl) else 0.0}
 
-    def parallel_do(self, cls: int, method: int, args=None, stream=None) -> None:
+    def parallel_do(self, cls: int, method: int, args=None, stream=None, from_snapshot: bool = False) -> None:
+        """Run `method` on every live object of `cls` and its subclasses; with
+        from_snapshot, on the objects recorded by the last snapshot(cls)."""
         p, nb = _blob(args)
-        check(lib().smmo_parallel_do(self.h, cls, method, p, nb, _stream(stream)))
+        fn = lib().smmo_parallel_do_snapshot if from_snapshot else lib().smmo_parallel_do
+        check(fn(self.h, cls, method, p, nb, _stream(stream)))
+
+    def snapshot(self, cls: int, stream=None) -> None:
+        """Record the objects of `cls` (and subclasses) live now, for a later
+        parallel_do(..., from_snapshot=True)."""
+        check(lib().smmo_snapshot(self.h, cls, _stream(stream)))
 
     # -- dumps (synchronize)
     def dump_objects(self, cls: int, dtypes, stream=None):

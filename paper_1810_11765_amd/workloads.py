@@ -121,16 +121,40 @@ class LifeGrid:
             self.heap.parallel_new(self.AGENT, self.n_alive0, S.CTOR_ARRAYS,
                                    S.ctor_arrays([self._agent_cell, None]), stream=stream)
 
-    def step(self, stream=None):
-        self.heap.parallel_do(self.CELL, S.M_LIFE_PLAN, self.args, stream=stream)
-        self.heap.parallel_do(self.AGENT, S.M_LIFE_AGENT, self.args, stream=stream)
-        self.heap.parallel_do(self.CELL, S.M_LIFE_COMMIT, self.args, stream=stream)
+    def step(self, stream=None, side_stream=None):
+        """One step: Cell::plan, Agent::step, Cell::commit, in this order.
+
+        With side_stream, the agent phase runs on side_stream at the same time
+        as the commit phase on `stream`: the agents to visit are recorded
+        (snapshot) on side_stream while plan runs, commit waits for that
+        record, so the agents it creates are not visited, and the agent phase
+        reads the next state from bit 1 of the alive byte, which commit leaves
+        unchanged.  The two phases touch no common field, so the result is
+        that of the sequential order."""
+        if side_stream is None:
+            self.heap.parallel_do(self.CELL, S.M_LIFE_PLAN, self.args, stream=stream)
+            self.heap.parallel_do(self.AGENT, S.M_LIFE_AGENT, self.args, stream=stream)
+            self.heap.parallel_do(self.CELL, S.M_LIFE_COMMIT, self.args, stream=stream)
+            return
+        if (self.heap.num_blocks + 63) // 64 >= self.heap.get_launch()["list_min_words"]:
+            raise ValueError("concurrent phases need a heap below the block-list threshold (shared list buffer)")
+        main = stream if stream is not None else torch.cuda.current_stream()
+        side_stream.wait_stream(main)
+        self.heap.snapshot(self.AGENT, stream=side_stream)
+        recorded = torch.cuda.Event()
+        recorded.record(side_stream)
+        self.heap.parallel_do(self.CELL, S.M_LIFE_PLAN, self.args, stream=main)
+        side_stream.wait_stream(main)
+        self.heap.parallel_do(self.AGENT, S.M_LIFE_AGENT, self.args, stream=side_stream, from_snapshot=True)
+        main.wait_event(recorded)
+        self.heap.parallel_do(self.CELL, S.M_LIFE_COMMIT, self.args, stream=main)
+        main.wait_stream(side_stream)
 
     def state(self):
         """(alive grid uint8, agent age per cell with -1 where none)."""
         x, y, a = self.heap.dump_objects(self.CELL, [np.int32, np.int32, np.uint8])
         alive = np.zeros(self.W * self.H, dtype=np.uint8)
-        alive[y.astype(np.int64) * self.W + x] = a
+        alive[y.astype(np.int64) * self.W + x] = a & 1          # bit 0: the state (bit 1: next)
         cell, age = self.heap.dump_objects(self.AGENT, [np.int32, np.int32])
         ages = np.full(self.W * self.H, -1, dtype=np.int32)
         assert len(np.unique(cell)) == len(cell), "two agents on one cell"

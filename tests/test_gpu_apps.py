@@ -68,6 +68,58 @@ def test_life_full_size_parity_with_the_tuned_shape():
     _life_check(g, 512, 512, 200)
 
 
+def _tuned_life(seed=42):
+    import os
+    from paper_1810_11765_amd import smmo as S
+    from paper_1810_11765_amd import tune
+    path = os.path.join(os.path.dirname(S.__file__), "tuned_launch.json")
+    shape = tune.load(path, "life-like 512x512 200 steps") or {}
+    g = W().LifeGrid(seed=seed)
+    g.heap.set_launch(**{k: v for k, v in shape.items() if k in S.LAUNCH_FIELDS})
+    g.heap.set_tuning(0, shape.get("lookups", 5), 0)
+    return g
+
+
+@pytest.mark.parametrize("seed", [42, 7])
+def test_life_concurrent_phases_parity(seed):
+    """The agent phase on a second stream, concurrent with the commit phase
+    (snapshot of the agents while plan runs): same state as the oracle."""
+    say("life concurrent", seed)
+    g = _tuned_life(seed)
+    g.populate()
+    side = torch.cuda.Stream()
+    for s in range(1, 201):
+        g.step(side_stream=side)
+        if s in (1, 2, 50):
+            torch.cuda.synchronize()
+            _life_check(g, 512, 512, s)
+    torch.cuda.synchronize()
+    _life_check(g, 512, 512, 200)
+
+
+def test_life_concurrent_phases_in_a_graph():
+    """100 concurrent-phase steps captured once in a HIP graph over two
+    streams, replayed twice with host dumps in between: the state equals the
+    oracle's after 100 and after 200 steps."""
+    say("life concurrent graph")
+    g = _tuned_life(42)
+    g.populate()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    cap, side = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(graph, stream=cap):
+            for _ in range(100):
+                g.step(stream=cap, side_stream=side)
+    torch.cuda.synchronize()
+    _life_check(g, 512, 512, 0)                      # capture ran nothing
+    for rep in (1, 2):
+        graph.replay()
+        torch.cuda.synchronize()
+        _life_check(g, 512, 512, 100 * rep)
+    del graph
+
+
 @pytest.mark.parametrize("Wd,Hd,blocks", [(37, 23, 64), (130, 7, 64), (64, 64, 128)])
 def test_life_ragged_parity(Wd, Hd, blocks):
     say("life ragged", Wd, Hd)

@@ -112,3 +112,38 @@ def test_nbody_methods_refuse_a_class_with_subclasses():
     h = smmo.Heap([[4] * 5, {"fields": [4], "super": 0}], 16)
     with pytest.raises(smmo.SmmoError, match="subclasses"):
         h.parallel_do(0, smmo.M_NBODY_MOVE, smmo.NbodyArgs())
+
+
+@pytest.mark.parametrize("blocks", [128, 300_000])      # flat scan; level-1 block list
+def test_do_all_from_snapshot_skips_later_objects(blocks):
+    """smmo_snapshot then smmo_parallel_do_snapshot: objects created after the
+    snapshot, in the class or a subclass, are not visited; the recorded ones
+    are visited once."""
+    say("snapshot do-all", blocks)
+    smmo = S()
+    h = smmo.Heap(CLASSES, blocks)
+    edges = _populate(h)
+    first = int(edges[-1])
+    h.snapshot(0)
+    extra = [90, 45]                                    # more objects of class 0 and of its subclass 1
+    start = first
+    for t, n in enumerate(extra):
+        ids = torch.arange(start, start + n, dtype=torch.int32, device="cuda")
+        srcs = [ids, None, None, None][: len(h.classes[t])]
+        h.parallel_new(t, n, smmo.CTOR_ARRAYS, smmo.ctor_arrays(srcs))
+        start += n
+    assert h.status() == 0
+    visits = torch.zeros(start, dtype=torch.int32, device="cuda")
+    h.parallel_do(0, smmo.M_VISIT, smmo.VisitArgs(visits.data_ptr()), from_snapshot=True)
+    got = visits.cpu().numpy()
+    want = np.zeros(start, dtype=np.int32)
+    for t in (0, 1, 2):
+        want[edges[t]:edges[t + 1]] = 1
+    assert np.array_equal(got, want)
+    visits.zero_()
+    h.parallel_do(0, smmo.M_VISIT, smmo.VisitArgs(visits.data_ptr()))     # live now: everything in the subtree
+    want[first:] = 1
+    assert np.array_equal(visits.cpu().numpy(), want)
+    with pytest.raises(smmo.SmmoError, match="snapshot"):
+        h.parallel_do(0, smmo.M_AXPY, smmo.AxpyArgs(0.5, 1, 2, 0), from_snapshot=True)
+    check_heap(h, expect_live=[COUNTS[0] + extra[0], COUNTS[1] + extra[1], COUNTS[2], COUNTS[3]])
