@@ -30,18 +30,25 @@ struct BatchSched {         // host-written schedule
 
 constexpr uint32_t kBarrierSpin = 1u << 24;
 
+// Barrier among the workgroups of one instance.  Arrival is a release (this
+// workgroup's stores of the phase become visible at agent scope); the wait
+// polls the counter with relaxed loads and acquires once, after the last
+// poll: on gfx950 an agent-scope acquire invalidates the XCD's L2, so an
+// acquire on every poll would evict what the other workgroups there are
+// working on, once per poll.
 __device__ inline void instance_barrier(uint32_t* cnt, uint32_t target, uint32_t* status) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (++spins > kBarrierSpin) {
                 __hip_atomic_fetch_or(status, SMMO_STATUS_RETRY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
