@@ -91,9 +91,17 @@ __device__ inline bool bm_try_clear(const DevHeap& h, uint32_t b, uint64_t pos) 
 __device__ inline uint32_t rot_ffs(uint64_t w, uint32_t rot) {
     return (ctz64(rotr64(w, rot)) + rot) & 63;
 }
+// A set bit of w (w != 0) chosen uniformly by the 32 random bits r.
+__device__ inline uint32_t pick_set_bit(uint64_t w, uint32_t r) {
+    return nth_set_bit(w, (uint32_t)(((uint64_t)r * popc64(w)) >> 32));
+}
 
-// try_find_set() (Alg. 4), top-down from the single top word.  `seed` gives a
-// different rotation per level; it depends on the wave and changes per retry.
+// try_find_set() (Alg. 4), top-down from the single top word.  Where the
+// paper rotates the start of each level's find-first-set (Sec. 4.2), this
+// picks one of the word's set bits uniformly: the same spreading of waves
+// over the bits, without favouring bits that follow a long run of zeros.
+// `seed` gives different random bits per level; it depends on the wave and
+// changes per retry.  Without rotation (ablation), the first set bit.
 __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_t seed) {
     b = uni32(b);
     seed = uni64(seed);
@@ -105,7 +113,7 @@ __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_
     for (int l = (int)h.nlevels - 1; l >= 0; --l) {
         const uint64_t w = w_load(bm_word(h, b, (uint32_t)l, idx));
         if (!w) return kFail;
-        const uint32_t bit = rotate ? rot_ffs(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
+        const uint32_t bit = rotate ? pick_set_bit(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
         idx = (idx << 6) | bit;
     }
     return idx;
