@@ -694,8 +694,15 @@ def cpu_baseline():
         core.c2_run(a0, 512, 512, 200)
         steps += 200
     dt = time.perf_counter() - t0
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(steps / dt, 2), "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps // 200} full runs of 200 steps of the 512x512 Life-like grid"}
+            "sample": f"{steps // 200} full runs of 200 steps of the 512x512 Life-like grid",
+            "cpu_model": cpu}
 
 
 def main():
