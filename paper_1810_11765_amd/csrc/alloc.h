@@ -124,7 +124,10 @@ __device__ __forceinline__ uint64_t alloc_piece(const DevHeap& h, uint32_t cls, 
         uint64_t bid = kFail;
         for (uint32_t a = 0; a < h.lookups; ++a) {
             seed = splitmix64(seed);
-            bid = bm_try_find_set(h, bm_active(h, cls), seed);
+            // a whole-block request mostly finds no active block: the plain
+            // search fails at the top word in one round trip
+            bid = whole ? bm_try_find_set(h, bm_active(h, cls), seed)
+                        : bm_try_find_set_dense(h, bm_active(h, cls), seed);
             if (bid != kFail) break;
             w_count(h, SMMO_CNT_FIND_FAIL);
             // a request for a whole block or more fills a fresh block by

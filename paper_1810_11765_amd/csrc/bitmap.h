@@ -119,6 +119,30 @@ __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_
     return idx;
 }
 
+// try_find_set() for a bitmap expected to be dense at level 0 (the active
+// blocks of a class): with three or more levels, two random level-0 words are
+// read first, by two lanes in one round trip (instead of one per level), and a
+// set bit of a non-empty one is returned; only if both are empty does the
+// top-down search run.  A set bit found this way is as
+// valid as one found top-down (both come from reads that may be stale).
+__device__ inline uint64_t bm_try_find_set_dense(const DevHeap& h, uint32_t b, uint64_t seed) {
+    b = uni32(b);
+    seed = uni64(seed);
+    if (!(h.tune & (SMMO_TUNE_NO_ROTATE | SMMO_TUNE_FORCE_FAIL)) && h.nlevels >= 3 &&
+        __builtin_amdgcn_read_exec() == kOnes) {
+        const uint64_t r = splitmix64(seed ^ 0x5bd1e995ull);
+        const uint32_t lane = lane_id();
+        const uint64_t j = lane < 2 ? (((uint64_t)(uint32_t)(r >> (32 * lane)) * h.level_words[0]) >> 32) : 0;
+        const uint64_t wl = lane < 2 ? at_load(bm_word(h, b, 0, j)) : 0;
+        const uint64_t nz = ballot(wl != 0);
+        if (nz) {
+            const uint32_t i = nz == 3 ? (uint32_t)(seed >> 63) : ctz64(nz);
+            return (readlane64(j, i) << 6) | pick_set_bit(readlane64(wl, i), (uint32_t)seed);
+        }
+    }
+    return bm_try_find_set(h, b, seed);
+}
+
 // clear(): find and clear any set bit; kFail if a lookup finds none.  A
 // lost race for the bit found backs off before the next lookup.
 __device__ inline uint64_t bm_clear_any(const DevHeap& h, uint32_t b, uint64_t& seed) {
