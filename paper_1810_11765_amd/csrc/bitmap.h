@@ -86,12 +86,8 @@ __device__ inline bool bm_try_clear(const DevHeap& h, uint32_t b, uint64_t pos) 
     return true;
 }
 
-// Rotated find-first-set: first set bit at or after position `rot`, cyclically
-// (Sec. 4.2 "Bitmap Rotation").
-__device__ inline uint32_t rot_ffs(uint64_t w, uint32_t rot) {
-    return (ctz64(rotr64(w, rot)) + rot) & 63;
-}
-// A set bit of w (w != 0) chosen uniformly by the 32 random bits r.
+// A set bit of w (w != 0) chosen uniformly by the 32 random bits r: the
+// spreading that Sec. 4.2's bitmap rotation provides.
 __device__ inline uint32_t pick_set_bit(uint64_t w, uint32_t r) {
     return nth_set_bit(w, (uint32_t)(((uint64_t)r * popc64(w)) >> 32));
 }
@@ -123,8 +119,8 @@ __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_
 // blocks of a class): with three or more levels, two random level-0 words are
 // read first, by two lanes in one round trip (instead of one per level), and a
 // set bit of a non-empty one is returned; only if both are empty does the
-// top-down search run.  A set bit found this way is as
-// valid as one found top-down (both come from reads that may be stale).
+// top-down search run.  A set bit found this way is as valid as one found
+// top-down (both come from reads that may be stale).
 __device__ inline uint64_t bm_try_find_set_dense(const DevHeap& h, uint32_t b, uint64_t seed) {
     b = uni32(b);
     seed = uni64(seed);
