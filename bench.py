@@ -120,29 +120,37 @@ def life_bench(torch, workloads, steps, warmup):
     status = g.heap.status()
     same = all((a == b).all() for a, b in zip(g.state(), ge.state()))
     del graph
-    # per-kernel durations: the same K steps again from a fresh grid, each
-    # do-all bracketed by events on the stream it is launched on.  A spin
-    # kernel first holds the stream while the host queues every launch, so
-    # the GPU then runs them back to back and an event pair measures the
-    # kernel, not the host's launch latency (a do-all takes less time than its
-    # Python launch path).
+    # per-kernel durations: the same K steps again from a fresh grid.  Each
+    # do-all kernel is dispatched with a pair of HIP events on its stream that
+    # the dispatch itself records when the kernel starts and ends
+    # (smmo_time_next_doall), so an event pair measures the kernel alone, as
+    # the kernel trace does.  A spin kernel first holds the stream while the
+    # host queues every launch, so the GPU then runs them back to back.
     g2 = grid()
     g2.populate()
     torch.cuda.synchronize()
     hold_start = torch.cuda.Event()
     torch.cuda._sleep(HOLD_CYCLES)
     hold_start.record()
-    tm = Timer(torch)
+    own = {"plan": [], "agent": [], "commit": []}
+
+    def timed(name, cls, method):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g2.heap.time_next_doall(a, b)
+        g2.heap.parallel_do(cls, method, g2.args)
+        own[name].append((a, b))
     for _ in range(steps):
-        tm.run("plan", lambda: g2.heap.parallel_do(g2.CELL, S.M_LIFE_PLAN, g2.args))
-        tm.run("agent", lambda: g2.heap.parallel_do(g2.AGENT, S.M_LIFE_AGENT, g2.args))
-        tm.run("commit", lambda: g2.heap.parallel_do(g2.CELL, S.M_LIFE_COMMIT, g2.args))
+        timed("plan", g2.CELL, S.M_LIFE_PLAN)
+        timed("agent", g2.AGENT, S.M_LIFE_AGENT)
+        timed("commit", g2.CELL, S.M_LIFE_COMMIT)
     queued_ahead = not hold_start.query()            # the spin was still running when the last launch was queued
     torch.cuda.synchronize()
-    per = {k: sum(tm.ms(k)) / steps for k in ("plan", "agent", "commit")}
+    names = ("plan", "agent", "commit")
+    own_ms = {k: [a.elapsed_time(b) for a, b in own[k]] for k in names}
+    per = {k: sum(own_ms[k]) / steps for k in names}
     return ms_step, per, status, {"eager_steps_s": round(1e3 / ms_eager, 2), "graph_equals_eager": bool(same),
                                   "launch": g.heap.get_launch(), "lookups": lookups, "events_queued_ahead": queued_ahead,
-                                  "kernel_max_ms": {k: round(max(tm.ms(k)), 5) for k in ("plan", "agent", "commit")}}
+                                  "kernel_max_ms": {k: round(max(own_ms[k]), 5) for k in names}}
 
 
 def roofline_for(per_ms):
@@ -153,8 +161,8 @@ def roofline_for(per_ms):
              the cell -> handle table (8, read by its 8 neighbours) = 18 B
       commit per cell: x, y (8) + alive read/write (2) = 10 B (+ 8 B per birth)
       agent  per agent: cell, age (8) + age write (4) + table entry (8) + alive (1)
-    The dominant kernel is the one with the largest event-timed share of the
-    step (the commit, whose births run the allocator: a chain of dependent
+    The dominant kernel is the one with the largest share of the step (kernel
+    durations recorded by the dispatches themselves) (the commit, whose births run the allocator: a chain of dependent
     agent-scope round trips, so it sits far below this bound).
     """
     name = max(per_ms, key=per_ms.get)

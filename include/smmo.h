@@ -399,6 +399,16 @@ int smmo_snapshot(smmo_heap* heap, uint32_t cls, void* stream);
 int smmo_parallel_do_snapshot(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
                               uint64_t args_bytes, void* stream);
 
+/* Measurement hook: the next generic do-all kernel this heap launches (the
+ * method's kernel of smmo_parallel_do or smmo_parallel_do_snapshot, not a
+ * snapshot, block-list or streaming-sweep pass) is dispatched with
+ * hipExtLaunchKernelGGL so that `start_event` and `stop_event` (hipEvent_t
+ * handles owned by the caller, created with timing enabled) record when the
+ * kernel itself starts and ends; hipEventElapsedTime then gives its duration
+ * without the queueing around it.  Applies to one launch; null events cancel
+ * a pending request.  A measurement aid; it changes no result. */
+int smmo_time_next_doall(smmo_heap* heap, void* start_event, void* stop_event);
+
 /* Live objects of class `cls`.  Synchronizes the stream. */
 int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream);
 

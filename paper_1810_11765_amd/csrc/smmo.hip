@@ -2,6 +2,7 @@
 // checking, kernel dispatch.  Every compute step runs in the kernels of
 // kernels.h / methods.h; this file only lays out memory and launches them.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdarg>
@@ -31,6 +32,7 @@ struct smmo_heap {
     uint64_t bytes;
     smmo_launch launch;    // effective launch shape
     uint32_t cus;          // compute units of the device
+    hipEvent_t time_start = nullptr, time_stop = nullptr;   // smmo_time_next_doall, pending
 };
 
 namespace {
@@ -296,7 +298,14 @@ int launch_doall_one(smmo_heap* H, uint32_t cls, const typename M::Args& a, bool
         grid = (unsigned)((std::min<uint64_t>(std::min<uint64_t>(H->hdr.num_blocks, 16384),
                                               (uint64_t)H->cus * H->launch.doall_waves_per_cu) + 3) / 4);
     }
-    k_doall<M, kSnap><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, R, nR, a);
+    if (H->time_start || H->time_stop) {
+        // the kernel's own start and end, recorded by the dispatch itself
+        hipExtLaunchKernelGGL((k_doall<M, kSnap>), dim3(grid), dim3(kBlockThreads), 0, s, H->time_start,
+                              H->time_stop, 0, H->dev, cls, s_log2, nunits, R, nR, a);
+        H->time_start = H->time_stop = nullptr;
+    } else {
+        k_doall<M, kSnap><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, R, nR, a);
+    }
     LAUNCH_CHECK("k_doall");
     return SMMO_OK;
 }
@@ -645,6 +654,13 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
 int smmo_parallel_do_snapshot(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
                               uint64_t args_bytes, void* stream) {
     return parallel_do(heap, cls, method_id, args, args_bytes, stream, true);
+}
+
+int smmo_time_next_doall(smmo_heap* heap, void* start_event, void* stop_event) {
+    if (!heap) return fail(SMMO_EINVAL, "null heap");
+    heap->time_start = static_cast<hipEvent_t>(start_event);
+    heap->time_stop = static_cast<hipEvent_t>(stop_event);
+    return SMMO_OK;
 }
 
 int smmo_snapshot(smmo_heap* heap, uint32_t cls, void* stream) {

@@ -134,6 +134,7 @@ def lib():
             "smmo_parallel_do": ([P, u32, u32, P, u64, P], i),
             "smmo_parallel_do_snapshot": ([P, u32, u32, P, u64, P], i),
             "smmo_snapshot": ([P, u32, P], i),
+            "smmo_time_next_doall": ([P, P, P], i),
             "smmo_parallel_destroy": ([P, P, u64, u32, P], i),
             "smmo_occupancy": ([P, P, P, P, P], i),
             "smmo_atomic_probe": ([P, u64, u32, u64, u32, P], i),
@@ -336,6 +337,14 @@ class Heap:
         p, nb = _blob(args)
         fn = lib().smmo_parallel_do_snapshot if from_snapshot else lib().smmo_parallel_do
         check(fn(self.h, cls, method, p, nb, _stream(stream)))
+
+    def time_next_doall(self, start, stop) -> None:
+        """Make the next do-all kernel record torch events `start` and `stop`
+        (enable_timing=True) at its own start and end."""
+        for e in (start, stop):
+            if e.cuda_event == 0:                  # torch creates the HIP event on first record
+                e.record()
+        check(lib().smmo_time_next_doall(self.h, C.c_void_p(start.cuda_event), C.c_void_p(stop.cuda_event)))
 
     def snapshot(self, cls: int, stream=None) -> None:
         """Record the objects of `cls` (and subclasses) live now, for a later

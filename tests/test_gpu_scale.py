@@ -235,3 +235,30 @@ def test_launch_shape_rejects_out_of_range():
             h.set_launch(**bad)
     assert h.get_launch() == {"doall_waves_per_cu": 32, "doall_units": 16384, "list_min_words": 4096,
                               "sweep_waves_per_cu": 128, "sweep_groups": 4}
+
+
+def test_timing_hook_records_the_kernel_alone():
+    """smmo_time_next_doall: the next do-all kernel records the two events at
+    its own start and end; its duration is positive and within the events
+    recorded around the call, and the do-all's result is unchanged."""
+    say("timing hook")
+    S_ = S()
+    h = S_.Heap([[4, 4, 4]], 256)
+    n = 256 * 21 - 7
+    ids = torch.arange(n, dtype=torch.int32, device="cuda")
+    h.parallel_new(0, n, S_.CTOR_ARRAYS, S_.ctor_arrays([ids, None, None]))
+    for _ in range(2):                                   # the hook applies to one launch only
+        visits = torch.zeros(n, dtype=torch.int32, device="cuda")
+        outer_a, outer_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        h.time_next_doall(a, b)
+        outer_a.record()
+        h.parallel_do(0, S_.M_VISIT, S_.VisitArgs(visits.data_ptr()))
+        outer_b.record()
+        torch.cuda.synchronize()
+        own, around = a.elapsed_time(b), outer_a.elapsed_time(outer_b)
+        assert 0.0 < own <= around + 1e-3, (own, around)
+        assert (visits.cpu().numpy() == 1).all()
+    visits.zero_()
+    h.parallel_do(0, S_.M_VISIT, S_.VisitArgs(visits.data_ptr()))  # no pending request: a plain launch
+    assert (visits.cpu().numpy() == 1).all()
