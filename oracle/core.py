@@ -115,6 +115,27 @@ def c4_accel(x, y, m, sel, G=1e-6):
     return ax, ay
 
 
+def c4_run_grid(ids, x, y, vx, vy, m, steps, G=1e-6, dt=1e-3, merge_dist=1e-4, cell=1.0 / 1024,
+                checkpoints=(), on_checkpoint=None):
+    """`steps` whole steps (grid merge, force, move) of a large state; after
+    each step listed in `checkpoints`, on_checkpoint(step, arrays) is called
+    with the survivors (ascending id).  Returns the final arrays."""
+    L = lib()
+    if not hasattr(L, "_step_grid_sig"):
+        L.or_c4_step_grid.argtypes = [C.c_int64] + [C.c_void_p] * 6 + [C.c_float] * 3 + [C.c_double, C.c_void_p]
+        L.or_c4_step_grid.restype = C.c_int64
+        L._step_grid_sig = True
+    arrs = [np.ascontiguousarray(a).copy() for a in (ids, x, y, vx, vy, m)]
+    assert arrs[0].dtype == np.int32 and all(a.dtype == np.float32 for a in arrs[1:])
+    n = len(arrs[0])
+    npairs = np.zeros(1, dtype=np.int64)
+    for s in range(1, steps + 1):
+        n = L.or_c4_step_grid(n, *[_p(a) for a in arrs], G, dt, merge_dist, cell, _p(npairs))
+        if on_checkpoint is not None and s in checkpoints:
+            on_checkpoint(s, tuple(a[:n] for a in arrs))
+    return tuple(a[:n].copy() for a in arrs)
+
+
 def c4_merge_grid(ids, x, y, vx, vy, m, merge_dist=1e-4, cell=1.0 / 1024):
     """Merge phase only (grid candidates, same float test); returns survivors and #pairs."""
     L = lib()

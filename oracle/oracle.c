@@ -273,6 +273,37 @@ static int64_t uf_find(int64_t* p, int64_t i)
     return i;
 }
 
+/* Phases (F) and (P) on the n bodies of a merged state (ascending id):
+ * a_i = sum over j != i in ascending id of s*(dx, dy), dx = x_j - x_i,
+ * d2 = dx*dx + dy*dy, s = (G*m_j) / (d2*sqrtf(d2)); v += a*dt; x += v*dt.
+ * The bodies' sums are independent; each runs over j in ascending order. */
+static void c4_force_move(int64_t n, float* x, float* y, float* vx, float* vy, const float* m,
+                          float G, float dt)
+{
+    float* ax = (float*)malloc(sizeof(float) * (size_t)(n ? n : 1));
+    float* ay = (float*)malloc(sizeof(float) * (size_t)(n ? n : 1));
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        float sx = 0.0f, sy = 0.0f;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            float dx = x[j] - x[i], dy = y[j] - y[i];
+            float d2 = dx * dx + dy * dy;
+            float s = (G * m[j]) / (d2 * sqrtf(d2));
+            sx = sx + s * dx;
+            sy = sy + s * dy;
+        }
+        ax[i] = sx; ay[i] = sy;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        vx[i] = vx[i] + ax[i] * dt;
+        vy[i] = vy[i] + ay[i] * dt;
+        x[i] = x[i] + vx[i] * dt;
+        y[i] = y[i] + vy[i] * dt;
+    }
+    free(ax); free(ay);
+}
+
 int64_t or_c4_step(int64_t n, int32_t* id, float* x, float* y, float* vx, float* vy, float* m,
                    float G, float dt, float merge_dist, int64_t* npairs_out)
 {
@@ -314,29 +345,7 @@ int64_t or_c4_step(int64_t n, int32_t* id, float* x, float* y, float* vx, float*
     n = k;
     free(par); free(ms); free(px); free(py); free(seen);
 
-    /* (F) all pairs, ascending j */
-    float* ax = (float*)malloc(sizeof(float) * (size_t)(n ? n : 1));
-    float* ay = (float*)malloc(sizeof(float) * (size_t)(n ? n : 1));
-    #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
-        float sx = 0.0f, sy = 0.0f;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            float dx = x[j] - x[i], dy = y[j] - y[i];
-            float d2 = dx * dx + dy * dy;
-            float s = (G * m[j]) / (d2 * sqrtf(d2));
-            sx = sx + s * dx;
-            sy = sy + s * dy;
-        }
-        ax[i] = sx; ay[i] = sy;
-    }
-    for (int64_t i = 0; i < n; ++i) {
-        vx[i] = vx[i] + ax[i] * dt;
-        vy[i] = vy[i] + ay[i] * dt;
-        x[i] = x[i] + vx[i] * dt;
-        y[i] = y[i] + vy[i] * dt;
-    }
-    free(ax); free(ay);
+    c4_force_move(n, x, y, vx, vy, m, G, dt);
     return n;
 }
 
@@ -431,4 +440,15 @@ int64_t or_c4_merge_grid(int64_t n, int32_t* id, float* x, float* y, float* vx, 
     }
     free(rec); free(par); free(ms); free(px); free(py); free(cnt);
     return k;
+}
+
+/* One whole step (M), (F), (P) with the merge's candidate pairs taken from the
+ * grid of or_c4_merge_grid: the same result as or_c4_step (the grid only
+ * narrows which pairs are tested), at a cost that large states can afford. */
+int64_t or_c4_step_grid(int64_t n, int32_t* id, float* x, float* y, float* vx, float* vy, float* m,
+                        float G, float dt, float merge_dist, double cell, int64_t* npairs_out)
+{
+    n = or_c4_merge_grid(n, id, x, y, vx, vy, m, merge_dist, cell, npairs_out);
+    c4_force_move(n, x, y, vx, vy, m, G, dt);
+    return n;
 }

@@ -98,6 +98,39 @@ def test_alloc_microbench_parity(seed):
         check_heap(wl.heap, expect_live=[262144])
 
 
+@pytest.mark.parametrize("seed", [42, 5])
+def test_capacity_one_class_churn_matches_oracle(seed):
+    """A class of capacity 1 (44-byte objects next to a 1-byte class: N =
+    floor(64 * 1 / 44) = 1): every allocation takes a whole block and every
+    destruction is both FIRST and EMPTY (App. A.1 / Alg. 7), so the block is
+    set active and then invalidated and freed at once.  The alloc microbench
+    rounds (sweep + churn) on it, bit-exact against the oracle."""
+    smmo = S()
+    nthreads, per, rounds = 1000, 2, 4
+    classes = [[1], [4, 4, 4, 8, 8, 8, 8]]
+    h = smmo.Heap(classes, nthreads * per + 130)
+    assert h.capacity(1) == 1 and h.capacity(0) == 64
+    ids, x, v = inputs.alloc_bench_initial(seed, nthreads, per)
+    src = [torch.from_numpy(a).cuda() for a in (ids, x, v)] + [None] * 4
+    say("capacity 1 alloc", seed)
+    h.parallel_alloc(1, nthreads, per, smmo.CTOR_ARRAYS, smmo.ctor_arrays(src))
+    s = check_heap(h, expect_live=[0, nthreads * per])
+    assert s["blocks"] == [0, nthreads * per]
+    want = _oracle_states(seed, nthreads, per, rounds)
+    dt = [np.int32, np.float32, np.float32] + [np.uint64] * 4
+    for r in range(rounds):
+        say("capacity 1 round", seed, r)
+        h.parallel_do(1, smmo.M_AXPY, smmo.AxpyArgs(0.5, 1, 2, 0))
+        h.parallel_do(1, smmo.M_CHURN, smmo.ChurnArgs(seed, r, 0))
+        gi, gx, gv = h.dump_objects(1, dt)[:3]
+        o = np.argsort(gi, kind="stable")
+        wi, wx, wv = want[r]
+        assert np.array_equal(gi[o], wi), f"round {r}: live ids differ"
+        assert bits_equal(gx[o], wx) and bits_equal(gv[o], wv), f"round {r}: field values differ"
+        s = check_heap(h, expect_live=[0, nthreads * per])
+        assert s["blocks"] == [0, nthreads * per]
+
+
 def test_every_live_object_visited_exactly_once():
     say("visit")
     smmo = S()

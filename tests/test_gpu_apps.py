@@ -33,7 +33,7 @@ def _life_check(g, W_, H_, steps_done):
     check_heap(g.heap, expect_live=[W_ * H_, int(oa.sum())])
 
 
-@pytest.mark.parametrize("seed", [42, 7])
+@pytest.mark.parametrize("seed", [42, 7, 1234])
 def test_life_full_size_parity(seed):
     """512 x 512 torus, density 0.3, 200 steps (16,384-block heap)."""
     say("life 512", seed)

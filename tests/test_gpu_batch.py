@@ -116,3 +116,65 @@ def test_serving_waits_for_memory():
     out = sv.serve(reqs, 20, arena, time_scale=0.0)         # all arrive at once
     _check(out["results"], reqs, 20)
     assert len(out["admit_delay_s"]) == 10 and out["admit_delay_s"].max() > 0
+
+
+def test_batched_three_level_bitmaps_match_oracle():
+    """Instances large enough for three-level block bitmaps (more than 4,096
+    blocks: sides 400 and 512) next to small ones, batched (graph replay) and
+    served: the top-down and level-0-probe searches of the batch kernel
+    against the oracle."""
+    sv = SV()
+    from paper_1810_11765_amd import inputs
+    from paper_1810_11765_amd.workloads import wator_blocks
+    reqs = []
+    for rid, (side, seed) in enumerate([(512, 101), (400, 102), (70, 103), (33, 104)]):
+        k0 = inputs.wator_initial(seed, side, side)
+        reqs.append(sv.Request(rid, side, seed, 0.01 * rid, k0))
+    assert wator_blocks(reqs[0].kind0) > 4096 and wator_blocks(reqs[1].kind0) > 4096
+    arena = S().Arena(sv.arena_bytes_for(reqs))
+    say("batched 3-level", [r.side for r in reqs])
+    results, dt, _ = sv.run_batched(reqs, 50, arena, per_launch=5, graph=True)
+    _check(results, reqs, 50)
+    say("served 3-level")
+    out = sv.serve(reqs, 50, arena, time_scale=1.0)
+    _check(out["results"], reqs, 50)
+
+
+def test_config_5_batched_and_served_against_oracle_goldens():
+    """The configuration as stated: 256 instances of seed 42, side log-uniform
+    in [64, 1024), 200 steps each, batched (persistent kernel, graph replay,
+    the bench's launch shape) and served (Poisson arrivals at 50/s).  Every
+    instance's final state hashes to the value the oracle stored in
+    tests/golden (written by tests/golden/make_goldens.py from oracle/ only)."""
+    import os
+    from golden.make_goldens import BATCH_FILE, read_batch, wator_hash
+    from paper_1810_11765_amd import tune
+    if not os.path.exists(BATCH_FILE):
+        pytest.fail("golden values missing: run python tests/golden/make_goldens.py batch")
+    golden = read_batch()
+    sv = SV()
+    reqs = sv.make_requests(seed=42, count=256)
+    assert sorted(golden) == [r.rid for r in reqs]
+    for r in reqs:
+        assert golden[r.rid][:2] == (r.side, r.seed)
+    shape = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5}
+    path = os.path.join(os.path.dirname(sv.__file__), "tuned_launch.json")
+    shape.update(tune.load(path, "predator-prey batched 256 instances 200 steps") or {})
+    arena = S().Arena(sv.arena_bytes_for(reqs))
+
+    def check(results, what):
+        bad = []
+        for r in reqs:
+            (kind, age, energy), status = results[r.rid]
+            assert status == 0, f"{what}: request {r.rid} device status {status:#x}"
+            if wator_hash(kind, age, energy) != golden[r.rid][2]:
+                bad.append((r.rid, r.side))
+        assert not bad, f"{what}: {len(bad)} instances differ from the oracle, e.g. {bad[:5]}"
+
+    say("config 5 batched", shape)
+    results, dt, _ = sv.run_batched(reqs, 200, arena, per_launch=shape["steps_per_launch"], graph=True,
+                                    wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"])
+    check(results, "batched")
+    say("config 5 served")
+    out = sv.serve(reqs, 200, arena, time_scale=1.0, wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"])
+    check(out["results"], "served")

@@ -139,3 +139,39 @@ def test_correctly_rounded_div_sqrt_against_ieee():
     ax, ay = core.c4_accel(x, y, m, np.arange(n), G=1.0)
     assert np.array_equal(vx.view(np.uint32), ax.view(np.uint32))
     assert np.array_equal(vy.view(np.uint32), ay.view(np.uint32))
+
+
+def test_nbody_config_100_steps_against_oracle_goldens():
+    """The configuration as stated: 262,144 bodies of seed 42, 100 steps.  At
+    steps 1, 10 and 100 the survivors are compared with the oracle's values
+    stored in tests/golden (written by tests/golden/make_goldens.py from
+    oracle/ only): exact survivor count, the sampled records within relative
+    1e-5 (field by field), and the SHA-256 of the whole canonical state, i.e.
+    every survivor bit for bit."""
+    from golden.make_goldens import NBODY_FILE, nbody_hash, read_nbody
+    import os
+    if not os.path.exists(NBODY_FILE):
+        pytest.fail("golden values missing: run python tests/golden/make_goldens.py nbody")
+    golden = read_nbody()
+    say("nbody config 262144 x 100 vs goldens")
+    sim = W().NBody(n=262144, seed=42)
+    sim.populate()
+    last = max(golden)
+    for s in range(1, last + 1):
+        sim.step()
+        if s not in golden:
+            continue
+        g = golden[s]
+        say("nbody step", s)
+        st = sim.state()
+        order = np.argsort(st[0], kind="stable")
+        st = tuple(a[order] for a in st)
+        assert len(st[0]) == g["count"], f"step {s}: {len(st[0])} survivors, oracle {g['count']}"
+        idx = np.searchsorted(st[0], np.array(sorted(g["sample"]), dtype=np.int32))
+        assert np.array_equal(st[0][idx], np.array(sorted(g["sample"]), dtype=np.int32)), f"step {s}: sampled ids"
+        got = np.stack([a[idx] for a in st[1:]], 1)
+        want = np.stack([g["sample"][k] for k in sorted(g["sample"])], 0)
+        rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-30)
+        assert rel.max() <= 1e-5, f"step {s}: sampled records rel err {rel.max()}"
+        assert nbody_hash(*st) == g["sha256"], f"step {s}: state differs from the oracle's (within 1e-5 on the sample)"
+    check_heap(sim.heap, expect_live=[golden[last]["count"]])

@@ -293,3 +293,58 @@ def test_grid_merge_equals_bruteforce_merge():
     assert nb == ng and nb >= 40
     for a, b in zip(brute, grid):
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_c4_accel_equals_the_force_phase_of_a_step_bit_for_bit():
+    """c4_accel (used to check large states body by body) is the force phase
+    of c4_step: with bodies at rest, dt = 1 and no close pairs, a step sets
+    v = 0 + a*1 = a exactly, so the step's velocities are the accelerations."""
+    n = 700
+    x, y, vx, vy, m = inputs.nbody_initial(11, n)
+    ids = np.arange(n, dtype=np.int32)
+    (i2, _, _, vx2, vy2, _), npairs = core.c4_step(ids, x, y, vx, vy, m, G=1e-6, dt=1.0)
+    assert npairs == 0 and len(i2) == n
+    ax, ay = core.c4_accel(x, y, m, np.arange(n), G=1e-6)
+    assert np.array_equal(ax.view(np.uint32), vx2.view(np.uint32))
+    assert np.array_equal(ay.view(np.uint32), vy2.view(np.uint32))
+    # a subset gives the same values as the full selection
+    sel = np.array([0, 5, n - 1, 321], dtype=np.int64)
+    sx, sy = core.c4_accel(x, y, m, sel, G=1e-6)
+    assert np.array_equal(sx.view(np.uint32), ax[sel].view(np.uint32))
+    assert np.array_equal(sy.view(np.uint32), ay[sel].view(np.uint32))
+
+
+@pytest.mark.parametrize("n,seed", [(2, 3), (64, 4), (512, 5)])
+def test_c4_accel_against_double_precision(n, seed):
+    """The float32 sum in ascending id stays within 2e-4 of the double-precision
+    sum, relative to the sum of the terms' magnitudes (n * 2^-24 bounds the
+    summation error, a few ulps the terms themselves)."""
+    x, y, _, _, m = inputs.nbody_initial(seed, n)
+    ax, ay = core.c4_accel(x, y, m, np.arange(n), G=1e-6)
+    X, Y, Mm = x.astype(np.float64), y.astype(np.float64), m.astype(np.float64)
+    dx = X[None, :] - X[:, None]
+    dy = Y[None, :] - Y[:, None]
+    d2 = dx * dx + dy * dy
+    np.fill_diagonal(d2, 1.0)
+    s = 1e-6 * Mm[None, :] / (d2 * np.sqrt(d2))
+    np.fill_diagonal(s, 0.0)
+    for got, comp in ((ax, s * dx), (ay, s * dy)):
+        want = comp.sum(1)
+        scale = np.abs(comp).sum(1)
+        assert (np.abs(got - want) <= 2e-4 * scale + 1e-30).all()
+
+
+def test_grid_step_equals_bruteforce_step():
+    """The whole grid-merge step (used for the full-size golden values) equals
+    the brute-force step over two steps, merges included."""
+    rng = np.random.default_rng(1)
+    n = 2500
+    x, y, vx, vy, m = inputs.nbody_initial(12, n)
+    _inject_close_pairs(x, y, rng, 25, chain=True)
+    ids = np.arange(n, dtype=np.int32)
+    a, _ = core.c4_step(ids, x, y, vx, vy, m)
+    a, _ = core.c4_step(*a)
+    b = core.c4_run_grid(ids, x, y, vx, vy, m, 2)
+    assert len(a[0]) < n
+    for p, q in zip(a, b):
+        assert np.array_equal(p.view(np.uint32), q.view(np.uint32))
