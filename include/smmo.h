@@ -399,14 +399,20 @@ int smmo_snapshot(smmo_heap* heap, uint32_t cls, void* stream);
 int smmo_parallel_do_snapshot(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
                               uint64_t args_bytes, void* stream);
 
-/* Measurement hook: the next generic do-all kernel this heap launches (the
- * method's kernel of smmo_parallel_do or smmo_parallel_do_snapshot, not a
- * snapshot, block-list or streaming-sweep pass) is dispatched with
+/* Measurement hook: the method kernel of the NEXT call of smmo_parallel_do
+ * or smmo_parallel_do_snapshot on this heap (its first method kernel when the
+ * class has subclasses; the streaming kernel of SMMO_M_AXPY; the force kernel
+ * of SMMO_M_NBODY_FORCE; not a snapshot or block-list pass) is dispatched with
  * hipExtLaunchKernelGGL so that `start_event` and `stop_event` (hipEvent_t
  * handles owned by the caller, created with timing enabled) record when the
  * kernel itself starts and ends; hipEventElapsedTime then gives its duration
- * without the queueing around it.  Applies to one launch; null events cancel
- * a pending request.  A measurement aid; it changes no result. */
+ * without the queueing around it.  The request is consumed by that call
+ * whatever it launches (a call that fails validation, or a method without a
+ * timed kernel such as SMMO_M_NBODY_RESOLVE, records nothing), and every
+ * other entry point taking this heap drops a pending request, so a request
+ * never attaches to a later, unrelated kernel.  The events must stay valid
+ * until that do-all call has returned; null events cancel a pending request.
+ * A measurement aid; it changes no result. */
 int smmo_time_next_doall(smmo_heap* heap, void* start_event, void* stop_event);
 
 /* Live objects of class `cls`.  Synchronizes the stream. */

@@ -30,8 +30,19 @@ def lib():
         L.or_c3_run.restype = None
         L.or_c4_step.argtypes = [i64, P, P, P, P, P, P, f32, f32, f32, P]; L.or_c4_step.restype = i64
         L.or_c4_accel.argtypes = [i64, P, P, P, f32, i64, P, P, P]; L.or_c4_accel.restype = None
+        L.or_threads.argtypes = []; L.or_threads.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]; L.or_set_threads.restype = None
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().or_set_threads(n)
 
 
 def _p(a: np.ndarray):

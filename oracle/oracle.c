@@ -30,6 +30,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 /* ------------------------------------------------------------------ RNG -- */
 
@@ -50,6 +51,10 @@ uint64_t or_ctr(uint64_t seed, uint64_t step, uint64_t id, uint64_t stream)
     h = or_splitmix64(h ^ step);
     return or_splitmix64(h ^ id);
 }
+
+/* Threads the OpenMP loops below use (the CPU-baseline leg reports it). */
+int or_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 static float u01(uint64_t h) { return (float)(h >> 40) * (1.0f / 16777216.0f); }
 static uint32_t choice(uint64_t h, uint32_t k) { return (uint32_t)((h >> 32) % k); }
@@ -123,6 +128,10 @@ void or_c2_run(int32_t W, int32_t H, int32_t steps, uint8_t* alive, int32_t* age
     for (int64_t c = 0; c < n; ++c)
         age[c] = alive[c] ? 0 : -1;
     for (int32_t s = 0; s < steps; ++s) {
+        /* every cell's next state depends on the current grid only, and
+         * every cell's update on its own entries: both loops split over
+         * threads without changing a result */
+        #pragma omp parallel for schedule(static)
         for (int32_t y = 0; y < H; ++y)
             for (int32_t x = 0; x < W; ++x) {
                 int cnt = 0;
@@ -135,6 +144,7 @@ void or_c2_run(int32_t W, int32_t H, int32_t steps, uint8_t* alive, int32_t* age
                 uint8_t a = alive[(int64_t)y * W + x];
                 next[(int64_t)y * W + x] = (uint8_t)(a ? (cnt == 2 || cnt == 3) : (cnt == 3));
             }
+        #pragma omp parallel for schedule(static)
         for (int64_t c = 0; c < n; ++c) {
             if (alive[c]) {                        /* agent lives here */
                 if (next[c]) age[c] += 1;

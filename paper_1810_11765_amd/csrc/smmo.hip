@@ -33,6 +33,20 @@ struct smmo_heap {
     smmo_launch launch;    // effective launch shape
     uint32_t cus;          // compute units of the device
     hipEvent_t time_start = nullptr, time_stop = nullptr;   // smmo_time_next_doall, pending
+    hipEvent_t armed_start = nullptr, armed_stop = nullptr; // taken by the current do-all call
+};
+
+// A timing request (smmo_time_next_doall) belongs to the next do-all call on
+// the heap: that call arms it for its method kernel, and every other entry
+// point, or a do-all call that launches no timed kernel, drops it.
+struct TimingScope {
+    smmo_heap* H;
+    explicit TimingScope(smmo_heap* h, bool take) : H(h) {
+        if (!H) return;
+        if (take) { H->armed_start = H->time_start; H->armed_stop = H->time_stop; }
+        H->time_start = H->time_stop = nullptr;
+    }
+    ~TimingScope() { if (H) H->armed_start = H->armed_stop = nullptr; }
 };
 
 namespace {
@@ -298,11 +312,11 @@ int launch_doall_one(smmo_heap* H, uint32_t cls, const typename M::Args& a, bool
         grid = (unsigned)((std::min<uint64_t>(std::min<uint64_t>(H->hdr.num_blocks, 16384),
                                               (uint64_t)H->cus * H->launch.doall_waves_per_cu) + 3) / 4);
     }
-    if (H->time_start || H->time_stop) {
+    if (H->armed_start || H->armed_stop) {
         // the kernel's own start and end, recorded by the dispatch itself
-        hipExtLaunchKernelGGL((k_doall<M, kSnap>), dim3(grid), dim3(kBlockThreads), 0, s, H->time_start,
-                              H->time_stop, 0, H->dev, cls, s_log2, nunits, R, nR, a);
-        H->time_start = H->time_stop = nullptr;
+        hipExtLaunchKernelGGL((k_doall<M, kSnap>), dim3(grid), dim3(kBlockThreads), 0, s, H->armed_start,
+                              H->armed_stop, 0, H->dev, cls, s_log2, nunits, R, nR, a);
+        H->armed_start = H->armed_stop = nullptr;
     } else {
         k_doall<M, kSnap><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, R, nR, a);
     }
@@ -378,8 +392,9 @@ int launch_nbody(smmo_heap* H, uint32_t cls, uint32_t method, const void* args, 
             k_enum<<<1, 1024, 0, s>>>(H->dev, bm_allocated(cls), H->hdr.num_blocks, scratch_R(H),
                                        scratch_counter(H, 2));
             LAUNCH_CHECK("k_enum");
-            k_nbody_force<<<grid_for(H->hdr.num_blocks, 4), 256, 0, s>>>(H->dev, cls, scratch_R(H),
-                                                                         scratch_counter(H, 2), a);
+            hipExtLaunchKernelGGL(k_nbody_force, dim3(grid_for(H->hdr.num_blocks, 4)), dim3(256), 0, s,
+                                  H->armed_start, H->armed_stop, 0, H->dev, cls, scratch_R(H), scratch_counter(H, 2), a);
+            H->armed_start = H->armed_stop = nullptr;
             LAUNCH_CHECK("k_nbody_force");
             return SMMO_OK;
         default: return fail(SMMO_EINVAL, "unknown n-body method %u", method);
@@ -488,6 +503,7 @@ int smmo_heap_destroy(smmo_heap* heap) {
 }
 
 int smmo_heap_reset(smmo_heap* heap, void* stream) {
+    TimingScope timing(heap, false);
     if (!heap) return fail(SMMO_EINVAL, "null heap");
     return init_device(heap, S(stream));
 }
@@ -515,6 +531,7 @@ int smmo_layout_compute(const smmo_class_desc* cls, uint32_t ncls, uint32_t whic
 }
 
 int smmo_set_tuning(smmo_heap* heap, uint32_t flags, uint32_t lookups, uint32_t force_fail_ppm, void* stream) {
+    TimingScope timing(heap, false);
     if (!heap) return fail(SMMO_EINVAL, "null heap");
     if (lookups < 1 || lookups > 64) return fail(SMMO_EINVAL, "lookups must be 1..64");
     if (force_fail_ppm > 1000000) return fail(SMMO_EINVAL, "force_fail_ppm must be <= 1e6");
@@ -534,6 +551,7 @@ int smmo_set_tuning(smmo_heap* heap, uint32_t flags, uint32_t lookups, uint32_t 
 
 int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_id, const void* args,
                       uint64_t args_bytes, void* stream) {
+    TimingScope timing(heap, false);
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     if (n == 0) return SMMO_OK;
@@ -547,6 +565,7 @@ int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_i
 
 int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32_t per_thread, uint32_t ctor_id,
                         const void* args, uint64_t args_bytes, void* stream) {
+    TimingScope timing(heap, false);
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     if (nthreads == 0 || per_thread == 0) return SMMO_OK;
@@ -563,6 +582,7 @@ int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32
 
 int smmo_parallel_destroy(smmo_heap* heap, const uint64_t* refs, uint64_t nthreads, uint32_t per_thread,
                           void* stream) {
+    TimingScope timing(heap, false);
     if (!heap) return fail(SMMO_EINVAL, "null heap");
     if (nthreads == 0 || per_thread == 0) return SMMO_OK;
     if (!refs) return fail(SMMO_EINVAL, "null refs");
@@ -575,6 +595,7 @@ int smmo_parallel_destroy(smmo_heap* heap, const uint64_t* refs, uint64_t nthrea
 
 static int parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args, uint64_t args_bytes,
                        void* stream, bool from_snapshot) {
+    TimingScope timing(heap, true);
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     hipStream_t s = S(stream);
@@ -595,10 +616,15 @@ static int parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const 
             const uint64_t waves = std::min<uint64_t>(nwords, (uint64_t)heap->cus * heap->launch.sweep_waves_per_cu);
             const unsigned grid = (unsigned)((waves + 3) / 4);
             for (uint32_t i = 0; i < n; ++i) {
+                hipEvent_t e0 = heap->armed_start, e1 = heap->armed_stop;
+                heap->armed_start = heap->armed_stop = nullptr;
                 switch (heap->launch.sweep_groups) {
-                    case 1: k_doall_axpy<1><<<grid, kBlockThreads, 0, s>>>(heap->dev, cl[i], nwords, a); break;
-                    case 2: k_doall_axpy<2><<<grid, kBlockThreads, 0, s>>>(heap->dev, cl[i], nwords, a); break;
-                    default: k_doall_axpy<4><<<grid, kBlockThreads, 0, s>>>(heap->dev, cl[i], nwords, a); break;
+                    case 1: hipExtLaunchKernelGGL((k_doall_axpy<1>), dim3(grid), dim3(kBlockThreads), 0, s, e0, e1, 0,
+                                                  heap->dev, cl[i], nwords, a); break;
+                    case 2: hipExtLaunchKernelGGL((k_doall_axpy<2>), dim3(grid), dim3(kBlockThreads), 0, s, e0, e1, 0,
+                                                  heap->dev, cl[i], nwords, a); break;
+                    default: hipExtLaunchKernelGGL((k_doall_axpy<4>), dim3(grid), dim3(kBlockThreads), 0, s, e0, e1, 0,
+                                                   heap->dev, cl[i], nwords, a); break;
                 }
                 LAUNCH_CHECK("k_doall_axpy");
             }
@@ -664,6 +690,7 @@ int smmo_time_next_doall(smmo_heap* heap, void* start_event, void* stop_event) {
 }
 
 int smmo_snapshot(smmo_heap* heap, uint32_t cls, void* stream) {
+    TimingScope timing(heap, false);
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     uint32_t cl[SMMO_MAX_CLASSES];
@@ -674,6 +701,7 @@ int smmo_snapshot(smmo_heap* heap, uint32_t cls, void* stream) {
 }
 
 int smmo_live_count(smmo_heap* heap, uint32_t cls, uint64_t* out, void* stream) {
+    TimingScope timing(heap, false);
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     if (!out) return fail(SMMO_EINVAL, "null out");
@@ -708,6 +736,7 @@ int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word,
 }
 
 int smmo_occupancy(smmo_heap* heap, uint64_t* used, uint64_t* slots, uint64_t* blocks, void* stream) {
+    TimingScope timing(heap, false);
     if (!heap) return fail(SMMO_EINVAL, "null heap");
     if (!used || !slots || !blocks) return fail(SMMO_EINVAL, "null output array");
     hipStream_t s = S(stream);
@@ -760,6 +789,7 @@ static void dump_range(const smmo_raw_header& h, uint32_t cls, const uint64_t* l
 
 static int dump_walk(smmo_heap* heap, uint32_t cls, void* const* bufs, uint64_t* refs, uint64_t cap,
                      uint64_t* n_out, void* stream) {
+    TimingScope timing(heap, false);
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     if (!n_out) return fail(SMMO_EINVAL, "null n_out");
@@ -824,6 +854,7 @@ int smmo_raw_bytes(const smmo_heap* heap, uint64_t* out) {
 }
 
 int smmo_dump_raw(smmo_heap* heap, void* host_buf, uint64_t bytes, void* stream) {
+    TimingScope timing(heap, false);
     if (!heap || !host_buf) return fail(SMMO_EINVAL, "null argument");
     if (bytes < heap->hdr.off_data)
         return fail(SMMO_EINVAL, "dump_raw: %llu bytes < %llu", (unsigned long long)bytes,
@@ -835,6 +866,7 @@ int smmo_dump_raw(smmo_heap* heap, void* host_buf, uint64_t bytes, void* stream)
 }
 
 int smmo_status(smmo_heap* heap, uint32_t* flags_out, void* stream) {
+    TimingScope timing(heap, false);
     if (!heap || !flags_out) return fail(SMMO_EINVAL, "null argument");
     hipStream_t s = S(stream);
     HIP_TRY(hipMemcpyAsync(flags_out, heap->dev.status, 4, hipMemcpyDeviceToHost, s));
@@ -843,6 +875,7 @@ int smmo_status(smmo_heap* heap, uint32_t* flags_out, void* stream) {
 }
 
 int smmo_clear_status(smmo_heap* heap, void* stream) {
+    TimingScope timing(heap, false);
     if (!heap) return fail(SMMO_EINVAL, "null argument");
     hipStream_t s = S(stream);
     // status word and counters: 256 bytes = 32 words, written by a kernel
@@ -852,6 +885,7 @@ int smmo_clear_status(smmo_heap* heap, void* stream) {
 }
 
 int smmo_stats(smmo_heap* heap, uint64_t* out, uint32_t n, void* stream) {
+    TimingScope timing(heap, false);
     if (!heap || !out || n > SMMO_CNT_NUM) return fail(SMMO_EINVAL, "bad argument");
     hipStream_t s = S(stream);
     HIP_TRY(hipMemcpyAsync(out, heap->dev.counters, 8ull * n, hipMemcpyDeviceToHost, s));

@@ -262,3 +262,34 @@ def test_timing_hook_records_the_kernel_alone():
     visits.zero_()
     h.parallel_do(0, S_.M_VISIT, S_.VisitArgs(visits.data_ptr()))  # no pending request: a plain launch
     assert (visits.cpu().numpy() == 1).all()
+
+
+def test_timing_request_is_dropped_by_other_calls_and_taken_by_the_sweep():
+    """A pending smmo_time_next_doall request belongs to the next do-all call:
+    another entry point in between (a live count) drops it, so the later
+    do-all leaves the events where they were; the streaming sweep and the
+    n-body force kernel take a request like the generic do-all."""
+    say("timing request scope")
+    S_ = S()
+    h = S_.Heap([[4, 4, 4]], 256)
+    n = 256 * 64
+    h.parallel_new(0, n, S_.CTOR_ZERO)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h.time_next_doall(a, b)                      # the binding records both once to create them
+    torch.cuda._sleep(50_000_000)                # tens of ms between those records and the do-all
+    mark = torch.cuda.Event(enable_timing=True)
+    mark.record()
+    assert h.live_count(0) == n                  # drops the request
+    h.parallel_do(0, S_.M_AXPY, S_.AxpyArgs(0.5, 1, 2, 0))
+    torch.cuda.synchronize()
+    assert a.elapsed_time(mark) > 1.0, "the do-all after another call recorded a dropped request"
+    # taken by the sweep itself
+    a2, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h.time_next_doall(a2, b2)
+    o1, o2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    o1.record()
+    h.parallel_do(0, S_.M_AXPY, S_.AxpyArgs(0.5, 1, 2, 0))
+    o2.record()
+    torch.cuda.synchronize()
+    own, around = a2.elapsed_time(b2), o1.elapsed_time(o2)
+    assert 0.0 < own <= around + 1e-3, (own, around)
