@@ -484,6 +484,27 @@ int smmo_batch_remove(smmo_batch* batch, uint32_t slot);
  * the instance set changed since the last call, in which case the schedule
  * is uploaded first (synchronously). */
 int smmo_batch_step(smmo_batch* batch, uint32_t steps, void* stream);
+/* Capture `launches` persistent-kernel launches of `steps_per_launch` steps
+ * each (the work of that many smmo_batch_step calls) into a HIP graph and
+ * instantiate it: the alloc -> do-all -> dealloc step of every admitted
+ * instance, replayed with one graph launch (Sec. 2.1's do-alls, batched).
+ * `stream` must be a created stream (not the null stream); nothing runs during
+ * the capture.  If the instance set or grid changed since the last step, the
+ * schedule is uploaded first (synchronously, outside the capture).  The
+ * captured kernels read the batch's tables at replay time, so a graph may be
+ * replayed only while the batch keeps the instance set and grid it was
+ * captured with: smmo_batch_graph_launch refuses it (SMMO_EINVAL) after
+ * smmo_batch_add_wator, smmo_batch_remove or smmo_batch_set_grid.  Each replay
+ * advances every instance by min(launches * steps_per_launch, its remaining
+ * steps).  The graph holds no device memory of its own besides what the HIP
+ * runtime keeps for an instantiated graph; free it with
+ * smmo_batch_graph_destroy before the batch. */
+typedef struct smmo_batch_graph smmo_batch_graph;
+int smmo_batch_capture_graph(smmo_batch* batch, uint32_t launches, uint32_t steps_per_launch, void* stream,
+                             smmo_batch_graph** out);
+/* Replay a captured graph on `stream` (asynchronous). */
+int smmo_batch_graph_launch(smmo_batch_graph* graph, void* stream);
+int smmo_batch_graph_destroy(smmo_batch_graph* graph);
 /* Remaining steps of every slot (0xFFFFFFFF for an empty slot), to host
  * memory of max_instances entries.  Synchronizes. */
 int smmo_batch_remaining(smmo_batch* batch, uint32_t* out, void* stream);

@@ -918,6 +918,13 @@ struct smmo_batch {
     std::vector<int> used;                      // slot in use
     std::vector<uint64_t> weight;               // grid cells of each slot
     bool dirty;
+    uint64_t generation = 0;                    // bumped whenever the instance set or grid changes
+};
+
+struct smmo_batch_graph {
+    hipGraphExec_t exec;
+    smmo_batch* batch;
+    uint64_t generation;                        // the batch's generation at capture
 };
 
 extern "C" {
@@ -1056,6 +1063,7 @@ int smmo_batch_add_wator(smmo_batch* B, smmo_heap* heap, const smmo_wator_args* 
     B->used[slot] = 1;
     B->weight[slot] = (uint64_t)args->width * (uint64_t)args->height;
     B->dirty = true;
+    ++B->generation;
     *slot_out = slot;
     return SMMO_OK;
 }
@@ -1065,6 +1073,7 @@ int smmo_batch_remove(smmo_batch* B, uint32_t slot) {
     B->used[slot] = 0;
     B->weight[slot] = 0;
     B->dirty = true;
+    ++B->generation;
     return SMMO_OK;
 }
 
@@ -1095,20 +1104,71 @@ static int batch_schedule(smmo_batch* B, hipStream_t s) {
     return SMMO_OK;
 }
 
-int smmo_batch_step(smmo_batch* B, uint32_t steps, void* stream) {
-    if (!B) return fail(SMMO_EINVAL, "null batch");
-    if (steps == 0) return SMMO_OK;
-    hipStream_t s = S(stream);
-    if (B->dirty) {
-        HIP_TRY(hipStreamSynchronize(s));
-        int rc = batch_schedule(B, s);
-        if (rc) return rc;
-    }
+// One persistent launch: the instance barrier counters are cleared by a
+// kernel (not a memset, so the pair can be captured and replayed).
+static int batch_launch(smmo_batch* B, uint32_t steps, hipStream_t s) {
     k_fill_u64<<<grid_for((B->max_inst + 1) / 2, 256), 256, 0, s>>>(reinterpret_cast<unsigned long long*>(B->d_bar),
                                                                      (B->max_inst + 1) / 2, 0);
     LAUNCH_CHECK("k_fill_u64");
     k_batch_wator<<<B->grid, 256, 0, s>>>(B->d_desc, B->d_prog, B->d_sched, B->d_wg_inst, B->d_bar, steps);
     LAUNCH_CHECK("k_batch_wator");
+    return SMMO_OK;
+}
+
+static int batch_prepare(smmo_batch* B, hipStream_t s) {
+    if (!B->dirty) return SMMO_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    return batch_schedule(B, s);
+}
+
+int smmo_batch_step(smmo_batch* B, uint32_t steps, void* stream) {
+    if (!B) return fail(SMMO_EINVAL, "null batch");
+    if (steps == 0) return SMMO_OK;
+    hipStream_t s = S(stream);
+    int rc = batch_prepare(B, s);
+    if (rc) return rc;
+    return batch_launch(B, steps, s);
+}
+
+int smmo_batch_capture_graph(smmo_batch* B, uint32_t launches, uint32_t steps_per_launch, void* stream,
+                             smmo_batch_graph** out) {
+    if (!B || !out) return fail(SMMO_EINVAL, "batch_capture_graph: null argument");
+    if (!stream) return fail(SMMO_EINVAL, "batch_capture_graph: capture needs a created stream, not the null stream");
+    if (launches == 0 || steps_per_launch == 0) return fail(SMMO_EINVAL, "batch_capture_graph: nothing to capture");
+    hipStream_t s = S(stream);
+    int rc = batch_prepare(B, s);
+    if (rc) return rc;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (uint32_t i = 0; i < launches && rc == SMMO_OK; ++i) rc = batch_launch(B, steps_per_launch, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t e_end = hipStreamEndCapture(s, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e_end != hipSuccess || !graph)
+        return fail(SMMO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e_end));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e_inst != hipSuccess) return fail(SMMO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e_inst));
+    *out = new smmo_batch_graph{exec, B, B->generation};
+    return SMMO_OK;
+}
+
+int smmo_batch_graph_launch(smmo_batch_graph* g, void* stream) {
+    if (!g) return fail(SMMO_EINVAL, "null batch graph");
+    if (g->batch->generation != g->generation)
+        return fail(SMMO_EINVAL, "batch graph: the batch's instances or grid changed since the capture");
+    HIP_TRY(hipGraphLaunch(g->exec, S(stream)));
+    return SMMO_OK;
+}
+
+int smmo_batch_graph_destroy(smmo_batch_graph* g) {
+    if (!g) return SMMO_OK;
+    const hipError_t e = hipGraphExecDestroy(g->exec);
+    delete g;
+    if (e != hipSuccess) return fail(SMMO_EHIP, "hipGraphExecDestroy: %s", hipGetErrorString(e));
     return SMMO_OK;
 }
 
@@ -1133,6 +1193,7 @@ int smmo_batch_set_grid(smmo_batch* B, uint32_t wg_per_cu) {
     const uint32_t w = wg_per_cu == 0 || wg_per_cu > B->per_cu ? B->per_cu : wg_per_cu;
     B->grid = B->cus * w;
     B->dirty = true;
+    ++B->generation;
     return SMMO_OK;
 }
 

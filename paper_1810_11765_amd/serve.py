@@ -130,20 +130,15 @@ def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bo
     torch.cuda.synchronize()
     launches = (steps + per_launch - 1) // per_launch
     if graph:
-        fleet.batch.step(per_launch)          # uploads the schedule outside capture
-        torch.cuda.synchronize()
-        launches -= 1
-        g = torch.cuda.CUDAGraph()
+        # every launch captured by the library into one HIP graph, replayed once
         s = torch.cuda.Stream()
-        with torch.cuda.stream(s):
-            with torch.cuda.graph(g, stream=s):
-                for _ in range(launches):
-                    fleet.batch.step(per_launch, stream=s)
+        g = fleet.batch.capture_graph(launches, per_launch, stream=s)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g.replay()
+        g.launch(stream=s)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        g.close()
     else:
         t0 = time.perf_counter()
         for _ in range(launches):

@@ -441,6 +441,8 @@ def _bind_batch():
         "smmo_batch_add_wator": ([P, P, P, u32, P, P], i), "smmo_batch_remove": ([P, u32], i),
         "smmo_batch_step": ([P, u32, P], i), "smmo_batch_remaining": ([P, P, P], i),
         "smmo_batch_grid": ([P, P], i), "smmo_batch_set_grid": ([P, u32], i),
+        "smmo_batch_capture_graph": ([P, u32, u32, P, P], i), "smmo_batch_graph_launch": ([P, P], i),
+        "smmo_batch_graph_destroy": ([P], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -517,6 +519,13 @@ class Batch:
         check(lib().smmo_batch_remaining(self.h, out.ctypes.data, _stream(stream)))
         return out
 
+    def capture_graph(self, launches: int, steps_per_launch: int = 1, stream=None) -> "BatchGraph":
+        """smmo_batch_capture_graph on `stream` (a created stream; torch's current
+        stream when None, which must then not be the null stream)."""
+        g = C.c_void_p()
+        check(lib().smmo_batch_capture_graph(self.h, launches, steps_per_launch, _stream(stream), C.byref(g)))
+        return BatchGraph(g)
+
     def grid(self) -> int:
         g = C.c_uint32()
         check(lib().smmo_batch_grid(self.h, C.byref(g)))
@@ -530,3 +539,24 @@ class Batch:
         if getattr(self, "h", None):
             lib().smmo_batch_destroy(self.h)
             self.h = None
+
+
+class BatchGraph:
+    """An instantiated HIP graph of persistent batch steps (smmo_batch_capture_graph)."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    def launch(self, stream=None) -> None:
+        check(lib().smmo_batch_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().smmo_batch_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -178,3 +178,50 @@ def test_config_5_batched_and_served_against_oracle_goldens():
     say("config 5 served")
     out = sv.serve(reqs, 200, arena, time_scale=1.0, wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"])
     check(out["results"], "served")
+
+
+def test_captured_batch_graph_replayed_several_times_matches_oracle():
+    """smmo_batch_capture_graph: one launch of 5 steps captured once and
+    replayed six times, with eager work (state dumps) and synchronizations
+    between the replays; after every replay each instance equals the oracle
+    at 5, 10, ... 30 steps.  Once the instance set changes, the graph is
+    refused instead of being replayed with a stale schedule."""
+    sv = SV()
+    S_ = S()
+    reqs = sv.make_requests(seed=11, count=6, lo=16, hi=90)
+    arena = S_.Arena(sv.arena_bytes_for(reqs))
+    fleet = sv.Fleet(arena, 8)
+    for r in reqs:
+        assert fleet.admit(r, 30)
+    stream = torch.cuda.Stream()
+    say("capture batch graph")
+    g = fleet.batch.capture_graph(1, 5, stream=stream)
+    torch.cuda.synchronize()
+    for rep in range(1, 7):
+        say("replay", rep)
+        g.launch(stream=stream)
+        torch.cuda.synchronize()
+        for slot, (r, w) in fleet.live.items():
+            kind, age, energy = w.state()
+            ok, oa, oe = core.c3_run(r.kind0, r.side, r.side, r.seed, 5 * rep)
+            assert np.array_equal(kind, ok), f"replay {rep}, request {r.rid}: occupancy differs"
+            assert np.array_equal(age[kind > 0], oa[ok > 0]), f"replay {rep}, request {r.rid}: ages differ"
+            assert np.array_equal(energy[kind == 2], oe[ok == 2]), f"replay {rep}, request {r.rid}: energies differ"
+    assert (fleet.batch.remaining()[:len(reqs)] == 0).all()
+    done = fleet.harvest()                       # removes every instance: the graph is now stale
+    assert len(done) == len(reqs) and all(st == 0 for _, _, st in done)
+    with pytest.raises(S_.SmmoError):
+        g.launch(stream=stream)
+    g.close()
+    fleet.close()
+
+
+def test_batch_graph_capture_rejects_the_null_stream():
+    S_ = S()
+    arena = S_.Arena(1 << 22)
+    b = S_.Batch(arena, 4)
+    import ctypes as C
+    out = C.c_void_p()
+    rc = S_.lib().smmo_batch_capture_graph(b.h, 1, 1, None, C.byref(out))
+    assert rc == -1 and not out.value
+    b.close()
