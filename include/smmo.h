@@ -223,6 +223,7 @@ typedef struct smmo_ctor_none {
 #define SMMO_M_CHURN 3u             /* alloc microbench round         (smmo_churn_args) */
 #define SMMO_M_MIX 4u               /* two-class churn (test method)  (smmo_mix_args)   */
 #define SMMO_M_STRESS 5u            /* alloc/destroy storm (test)     (smmo_stress_args) */
+#define SMMO_M_CHURN_API 6u         /* SMMO_M_CHURN written against smmo_device.h only      */
 #define SMMO_M_LIFE_PLAN 10u        /* Cell: next state, B3/S23       (smmo_life_args)  */
 #define SMMO_M_LIFE_AGENT 11u       /* Agent: die or age              (smmo_life_args)  */
 #define SMMO_M_LIFE_COMMIT 12u      /* Cell: birth of agents, commit  (smmo_life_args)  */

@@ -28,11 +28,14 @@ namespace smmo {
 
 // Bounds of the allocator's retry loops.  A wave gives up an allocation
 // after kOomRounds rounds that find neither an active block nor any free
-// block (the free bitmap's top word empty: OOM), or after kAllocIters
+// block (the free bitmap's top word empty: OOM; the bound is large because a
+// wave can also lose every freed block to others for a while: with 512 waves
+// churning two classes through 40 spare blocks, 4,096 such rounds were once
+// exceeded with free blocks coming and going), or after kAllocIters
 // iterations in all (RETRY: a livelock guard that contention alone does not
 // reach).  Once the status word holds OOM or RETRY, later requests give up
 // after a few rounds instead.
-constexpr uint32_t kOomRounds = 4096;
+constexpr uint32_t kOomRounds = 1u << 14;
 constexpr uint32_t kAllocIters = 1u << 18;
 
 // initialize_block<T> (Alg. 8): type and iteration word first, then, once

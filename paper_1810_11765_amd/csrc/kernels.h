@@ -126,6 +126,11 @@ struct Obj {
     template <class F>
     __device__ F& at(uint32_t off) const { return *reinterpret_cast<F*>(base + off + lane * sizeof(F)); }
     __device__ uint64_t self() const { return make_ref(cls, bid, lane); }
+    // device-side new, wave-collective; `salt` varies the allocator's random
+    // picks between calls of one method
+    __device__ __forceinline__ uint64_t alloc(uint32_t c, bool want, uint64_t salt = 0) const {
+        return wave_alloc(h, c, want, seed ^ salt);
+    }
 };
 
 // Parallel do-all (Sec. 3.7), enumeration fused in: the L0 words of

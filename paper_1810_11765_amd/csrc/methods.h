@@ -146,7 +146,7 @@ struct MChurn {
             nid = (int32_t)(((uint32_t)(a.round + 1) << 18) | ((uint32_t)id & 0x3FFFFu));
         }
         wave_destroy_self(o.h, o.cls, o.bid, die);
-        const uint64_t r = wave_alloc(o.h, o.cls, die, o.seed);
+        const uint64_t r = o.alloc(o.cls, die);
         if (die && r) {
             const uint64_t b = ref_block(r);
             const uint32_t s = ref_slot(r);
@@ -189,8 +189,8 @@ struct MMix {
             nid = (int32_t)(((uint32_t)(a.round + 1) << 18) | ((uint32_t)id & 0x3FFFFu));
         }
         wave_destroy_self(o.h, o.cls, o.bid, die);
-        const uint64_t ra = wave_alloc(o.h, a.cls_a, die && !to_b, o.seed);
-        const uint64_t rb = wave_alloc(o.h, a.cls_b, die && to_b, o.seed ^ 0x9e37ull);
+        const uint64_t ra = o.alloc(a.cls_a, die && !to_b);
+        const uint64_t rb = o.alloc(a.cls_b, die && to_b, 0x9e37ull);
         const uint64_t r = to_b ? rb : ra;
         if (die && r) {
             field_of<int32_t>(o.h, r, 0) = nid;
@@ -202,6 +202,9 @@ struct MMix {
 // Allocation storm on a tiny heap: many waves allocate into and free the same
 // few blocks at once, so blocks empty, get invalidated, freed and
 // re-initialized to the other class while other waves hold stale picks.
+// A wave frees its class-a objects before it asks for class-b ones: a wave
+// that waited for b while holding a could pin every spare block as a class-a
+// block (hold and wait), a true out-of-memory that no allocator can resolve.
 struct MStress {
     using Args = smmo_stress_args;
     static constexpr bool kSnapshot = false;
@@ -212,11 +215,12 @@ struct MStress {
         for (uint32_t k = 0; k < a.iters; ++k) {
             const bool act = o.live && o.lane < a.lanes;
             const bool to_b = splitmix64(a.seed ^ ((uint64_t)key << 20) ^ k) & 1;
-            const uint64_t ra = wave_alloc(o.h, a.cls_a, act && !to_b, o.seed ^ k);
-            const uint64_t rb = wave_alloc(o.h, a.cls_b, act && to_b, o.seed ^ (k << 8) ^ 0x51ull);
-            const uint64_t r = to_b ? rb : ra;
-            if (act && r) field_of<int32_t>(o.h, r, 0) = (int32_t)key;
-            wave_destroy(o.h, r, act && r != 0);
+            const uint64_t ra = o.alloc(a.cls_a, act && !to_b, k);
+            if (act && !to_b && ra) field_of<int32_t>(o.h, ra, 0) = (int32_t)key;
+            wave_destroy(o.h, ra, act && !to_b && ra != 0);
+            const uint64_t rb = o.alloc(a.cls_b, act && to_b, (k << 8) ^ 0x51ull);
+            if (act && to_b && rb) field_of<int32_t>(o.h, rb, 0) = (int32_t)key;
+            wave_destroy(o.h, rb, act && to_b && rb != 0);
         }
     }
 };
@@ -295,7 +299,7 @@ struct MLifeCommit {
             al = (uint8_t)((v & 2) ? 3 : 0);     // current <- next; bit 1 (next) stays for the agent phase
             c = o.at<int32_t>(p.cy) * a.width + o.at<int32_t>(p.cx);
         }
-        const uint64_t r = wave_alloc(o.h, a.agent_cls, born, o.seed);
+        const uint64_t r = o.alloc(a.agent_cls, born);
         if (born && r) {
             uint8_t* base = o.h.data + ref_block(r) * o.h.block_bytes;
             reinterpret_cast<int32_t*>(base + p.gc)[ref_slot(r)] = c;
@@ -364,7 +368,7 @@ struct MFishMove {
             win = t >= 0 && a.claim[t] == pos;
             breed = win && o.at<int32_t>(p.fa) >= a.fish_breed;
         }
-        const uint64_t child = wave_alloc(o.h, a.fish_cls, breed, o.seed);
+        const uint64_t child = o.alloc(a.fish_cls, breed);
         if (win) {
             a.claim[t] = INT32_MAX;
             a.occ[t] = o.self();
@@ -434,7 +438,7 @@ struct MSharkMove {
         wave_destroy(o.h, prey, prey != 0);
         if (prey) energy += a.eat_gain;
         breed = win && age >= a.shark_breed;
-        const uint64_t child = wave_alloc(o.h, a.shark_cls, breed, o.seed);
+        const uint64_t child = o.alloc(a.shark_cls, breed);
         energy -= 1;
         starve = o.live && energy <= 0;
         if (win) {

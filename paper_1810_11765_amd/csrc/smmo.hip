@@ -12,7 +12,9 @@
 #include <vector>
 
 #include "batch.h"
+#include "device_api.h"
 #include "methods.h"
+#include "methods_api.h"
 #include "nbody.h"
 
 #include <map>
@@ -633,6 +635,12 @@ static int parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const 
         case SMMO_M_DESTROY_ALL: return launch_doall<MDestroyAll>(heap, cls, nullptr, 0, s, from_snapshot);
         case SMMO_M_VISIT: return launch_doall<MVisit>(heap, cls, args, args_bytes, s, from_snapshot);
         case SMMO_M_CHURN: return launch_doall<MChurn>(heap, cls, args, args_bytes, s, from_snapshot);
+        case SMMO_M_CHURN_API: {
+            if (heap->hdr.nfields[cls] != 3 || heap->hdr.field_bytes[cls][0] != 4 || heap->hdr.field_bytes[cls][1] != 4 ||
+                heap->hdr.field_bytes[cls][2] != 4)
+                return fail(SMMO_EINVAL, "churn (device API): class needs fields {int32, float32, float32}");
+            return launch_doall<MChurnApi>(heap, cls, args, args_bytes, s, from_snapshot);
+        }
         case SMMO_M_MIX: {
             smmo_mix_args a;
             rc = unpack_args(a, args, args_bytes, "mix");

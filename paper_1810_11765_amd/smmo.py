@@ -27,6 +27,7 @@ M_DESTROY_ALL = 1
 M_VISIT = 2
 M_CHURN = 3
 M_MIX = 4
+M_CHURN_API = 6
 M_LIFE_PLAN = 10
 M_LIFE_AGENT = 11
 M_LIFE_COMMIT = 12

@@ -98,6 +98,28 @@ def test_alloc_microbench_parity(seed):
         check_heap(wl.heap, expect_live=[262144])
 
 
+@pytest.mark.parametrize("seed", [42, 7])
+def test_alloc_microbench_through_the_device_api_header(seed):
+    """The churn round written against include/smmo_device.h only
+    (smmo_alloc, smmo_destroy_self, smmo_field; SMMO_M_CHURN_API): the same
+    microbenchmark, bit-exact against the oracle after every round, on heaps
+    of 4,096 blocks (exactly full) and of 4,500 blocks (spare blocks)."""
+    smmo = S()
+    for blocks in (4096, 4500):
+        say("alloc microbench via device API", seed, blocks)
+        wl = W().AllocBench(seed=seed, num_blocks=blocks)
+        wl.initial_alloc()
+        want = _oracle_states(seed, 65536, 4, 6)
+        for r in range(6):
+            wl.sweep()
+            wl.heap.parallel_do(0, smmo.M_CHURN_API, smmo.ChurnArgs(seed, r, 0))
+            ids, x, v = wl.state()
+            wi, wx, wv = want[r]
+            assert np.array_equal(ids, wi), f"round {r}: live ids differ"
+            assert bits_equal(x, wx) and bits_equal(v, wv), f"round {r}: field values differ"
+            check_heap(wl.heap, expect_live=[262144])
+
+
 @pytest.mark.parametrize("seed", [42, 5])
 def test_capacity_one_class_churn_matches_oracle(seed):
     """A class of capacity 1 (44-byte objects next to a 1-byte class: N =
