@@ -400,6 +400,21 @@ int smmo_snapshot(smmo_heap* heap, uint32_t cls, void* stream);
 int smmo_parallel_do_snapshot(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
                               uint64_t args_bytes, void* stream);
 
+/* smmo_parallel_do for callers that cannot allocate device memory or have
+ * no spare heap scratch (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same do-all, but every block list it
+ * builds (big heaps' level-1 enumeration, the ordered list of the n-body
+ * force) and its counters live in one static device array of the library,
+ * 4 MiB + 1 KiB, allocated with the code object (no hipMalloc, hipFree or
+ * allocating library call).  Limit: heaps of at most 1,048,576 blocks
+ * (SMMO_EINVAL above).  The array is per GPU and shared by every call on
+ * that GPU and kept between calls: calls of this entry point that overlap on
+ * one GPU (other streams, other threads) race and must not be issued; the
+ * counters a call needs are cleared by its own kernels.  Otherwise as
+ * smmo_parallel_do, whose calls it may follow or precede on the stream. */
+int smmo_parallel_do_static_scratch(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
+                                    uint64_t args_bytes, void* stream);
+
 /* Measurement hook: the method kernel of the NEXT call of smmo_parallel_do
  * or smmo_parallel_do_snapshot on this heap (its first method kernel when the
  * class has subclasses; the streaming kernel of SMMO_M_AXPY; the force kernel

@@ -18,6 +18,7 @@
 #include "nbody.h"
 
 #include <map>
+#include <mutex>
 
 using namespace smmo;
 
@@ -36,7 +37,14 @@ struct smmo_heap {
     uint32_t cus;          // compute units of the device
     hipEvent_t time_start = nullptr, time_stop = nullptr;   // smmo_time_next_doall, pending
     hipEvent_t armed_start = nullptr, armed_stop = nullptr; // taken by the current do-all call
+    uint8_t* stage = nullptr;   // scratch of the current call when not the heap's own (static-scratch calls)
 };
+
+// Static device scratch of smmo_parallel_do_static_scratch (see below):
+// counters (1 KiB), then up to kStaticListBlocks block ids.
+constexpr uint64_t kStaticListBlocks = 1ull << 20;
+constexpr uint64_t kStaticScratchBytes = 1024 + 4 * kStaticListBlocks;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
 
 // A timing request (smmo_time_next_doall) belongs to the next do-all call on
 // the heap: that call arms it for its method kernel, and every other entry
@@ -214,14 +222,51 @@ int init_device(smmo_heap* H, hipStream_t s) {
     return SMMO_OK;
 }
 
+uint8_t* scratch_base(smmo_heap* H) { return H->stage ? H->stage : H->dev.scratch; }
 unsigned long long* scratch_counter(smmo_heap* H, int i) {
-    return reinterpret_cast<unsigned long long*>(H->dev.scratch) + i;
+    return reinterpret_cast<unsigned long long*>(scratch_base(H)) + i;
 }
 // scratch counters: 0 parallel_new's found, 1 live count, 2 n-body's found,
 // 3 block-list length, 8.. occupancy (3 per class).  R is the block list of
 // whichever call ran last on the heap's stream (calls on one heap are
 // stream-ordered).
-uint32_t* scratch_R(smmo_heap* H) { return reinterpret_cast<uint32_t*>(H->dev.scratch + kScratchHead); }
+uint32_t* scratch_R(smmo_heap* H) { return reinterpret_cast<uint32_t*>(scratch_base(H) + kScratchHead); }
+
+// ------------------------------------------------- static scratch ----
+// `scratch` (top of the file) is the device memory
+// smmo_parallel_do_static_scratch stages its block lists in instead of the
+// heap's scratch region, laid out like it (kScratchHead bytes of counters,
+// then the list).  Each GPU the library runs on holds one copy until the
+// process ends; every call on a GPU shares it.
+static_assert(kStaticScratchBytes == kScratchHead + 4 * kStaticListBlocks, "static scratch layout");
+
+// The array's device address on the current GPU, taken once per device with
+// hipGetSymbolAddress (in host code the array's name is not a device
+// address).
+std::mutex g_static_mu;
+std::map<int, uint8_t*> g_static_ptr;
+int static_scratch(uint8_t** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    auto it = g_static_ptr.find(dev);
+    if (it == g_static_ptr.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SMMO_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        it = g_static_ptr.emplace(dev, static_cast<uint8_t*>(p)).first;
+    }
+    *out = it->second;
+    return SMMO_OK;
+}
+
+// Routes a call's scratch to another buffer for its duration.
+struct StageScope {
+    smmo_heap* H;
+    StageScope(smmo_heap* h, uint8_t* p) : H(h) { H->stage = p; }
+    ~StageScope() { H->stage = nullptr; }
+};
 
 // Big heaps: list the blocks of allocated[cls] via level 1 into R, so that
 // the passes after it cost the class's blocks, not the heap's size.
@@ -688,6 +733,19 @@ int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const vo
 int smmo_parallel_do_snapshot(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
                               uint64_t args_bytes, void* stream) {
     return parallel_do(heap, cls, method_id, args, args_bytes, stream, true);
+}
+
+int smmo_parallel_do_static_scratch(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
+                                    uint64_t args_bytes, void* stream) {
+    if (!heap) return fail(SMMO_EINVAL, "null heap");
+    if (heap->hdr.num_blocks > kStaticListBlocks)
+        return fail(SMMO_EINVAL, "parallel_do_static_scratch: %llu blocks, the static scratch lists at most %llu",
+                    (unsigned long long)heap->hdr.num_blocks, (unsigned long long)kStaticListBlocks);
+    uint8_t* p = nullptr;
+    int rc = static_scratch(&p);
+    if (rc) return rc;
+    StageScope stage(heap, p);
+    return parallel_do(heap, cls, method_id, args, args_bytes, stream, false);
 }
 
 int smmo_time_next_doall(smmo_heap* heap, void* start_event, void* stop_event) {

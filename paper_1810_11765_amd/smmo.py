@@ -134,6 +134,7 @@ def lib():
             "smmo_parallel_alloc": ([P, u32, u64, u32, u32, P, u64, P], i),
             "smmo_parallel_do": ([P, u32, u32, P, u64, P], i),
             "smmo_parallel_do_snapshot": ([P, u32, u32, P, u64, P], i),
+            "smmo_parallel_do_static_scratch": ([P, u32, u32, P, u64, P], i),
             "smmo_snapshot": ([P, u32, P], i),
             "smmo_time_next_doall": ([P, P, P], i),
             "smmo_parallel_destroy": ([P, P, u64, u32, P], i),
@@ -332,11 +333,15 @@ class Heap:
         u, sl, b = list(used), list(slots), list(blocks)
         return {"used": u, "slots": sl, "blocks": b, "F": (1.0 - sum(u) / sum(sl)) if sum(sl) else 0.0}
 
-    def parallel_do(self, cls: int, method: int, args=None, stream=None, from_snapshot: bool = False) -> None:
+    def parallel_do(self, cls: int, method: int, args=None, stream=None, from_snapshot: bool = False,
+                    static_scratch: bool = False) -> None:
         """Run `method` on every live object of `cls` and its subclasses; with
-        from_snapshot, on the objects recorded by the last snapshot(cls)."""
+        from_snapshot, on the objects recorded by the last snapshot(cls); with
+        static_scratch, through smmo_parallel_do_static_scratch."""
         p, nb = _blob(args)
-        fn = lib().smmo_parallel_do_snapshot if from_snapshot else lib().smmo_parallel_do
+        assert not (from_snapshot and static_scratch)
+        fn = (lib().smmo_parallel_do_snapshot if from_snapshot else
+              lib().smmo_parallel_do_static_scratch if static_scratch else lib().smmo_parallel_do)
         check(fn(self.h, cls, method, p, nb, _stream(stream)))
 
     def time_next_doall(self, start, stop) -> None:
