@@ -569,6 +569,17 @@ int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word,
 
 /* Handle layout: bits 56-63 class id + 1, bits 6-49 block, bits 0-5 slot;
  * 0 is the null handle.  Host-side helpers. */
+/* Self-check of the arithmetic the n-body force kernel uses on its fast
+ * path (device_do, Sec. 2.1: correctly rounded sqrt and division where
+ * operands lie in ranges that need no scaling).  Adds to counts_dev[0] (a
+ * device uint64[2], cleared first) the float bit patterns in
+ * [lo_bits, hi_bits) whose fast square root differs from the correctly
+ * rounded one, and to counts_dev[1] the quotients that differ among `pairs`
+ * pseudo-random operand pairs from the fast ranges (seeded).  Both must be 0;
+ * the tests run it over the whole range [2^-40, 2^40). Asynchronous. */
+int smmo_check_force_arith(uint32_t lo_bits, uint32_t hi_bits, uint64_t pairs, uint64_t seed, uint64_t* counts_dev,
+                           void* stream);
+
 uint64_t smmo_ref_make(uint32_t cls, uint64_t block, uint32_t slot);
 uint32_t smmo_ref_class(uint64_t ref);
 uint64_t smmo_ref_block(uint64_t ref);

@@ -220,11 +220,70 @@ __global__ __launch_bounds__(1024) void k_nbody_resolve(DevHeap h, uint32_t cls,
 }
 
 // ---------------------------------------------------------------- FORCE ----
+// The force term of body i from body j (Listing 1 of Sec. 2.1 restated):
+// s = G m_j / (d2 * sqrt(d2)), d2 = dx*dx + dy*dy, then s*dx and s*dy are
+// added to i's sums in ascending key order of j.  Every operation is one
+// IEEE-754 rounding (correctly rounded sqrt and division), as in the oracle.
+//
+// Fast forms of the correctly rounded sqrt and division, for operands in
+// ranges where the general sequences' scaling and special-case steps do
+// nothing.  The force kernel takes them only where a per-lane range check
+// shows they apply, and the results are the IEEE results bit for bit there
+// (smmo_check_force_arith checks the square root on every float of the range
+// and the division on random pairs of it).
+//  * sqrt, for 2^-96 <= x < +inf: the hardware square root s (within one unit
+//    in the last place), then the rounding test on its neighbours: x minus
+//    the product of s with the neighbour below (above) tells on which side of
+//    the midpoint between them the exact root lies.
+//  * division a / b, for b and a / b normal, a >= 2^-100 and a / b < 2^96: the
+//    hardware reciprocal, one Newton-Raphson step on it, the quotient, then
+//    two corrections by the remainder computed with a fused multiply-add
+//    (Markstein's method; the same steps as the general sequence with its
+//    operand scaling and final fix-up left out).
+__device__ __forceinline__ float sqrt_cr_fast(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float below = __uint_as_float(__float_as_uint(s) - 1u);
+    const float above = __uint_as_float(__float_as_uint(s) + 1u);
+    const float r_below = __builtin_fmaf(-below, s, x);
+    const float r_above = __builtin_fmaf(-above, s, x);
+    float r = r_below <= 0.0f ? below : s;
+    r = r_above > 0.0f ? above : r;
+    return r;
+}
+__device__ __forceinline__ float div_cr_fast(float a, float b) {
+    float r = __builtin_amdgcn_rcpf(b);
+    const float e = __builtin_fmaf(-b, r, 1.0f);
+    r = __builtin_fmaf(e, r, r);
+    float q = a * r;
+    float rem = __builtin_fmaf(-b, q, a);
+    q = __builtin_fmaf(rem, r, q);
+    rem = __builtin_fmaf(-b, q, a);
+    return __builtin_fmaf(rem, r, q);
+}
+// Ranges of the fast path, as float bit patterns: d2 in [2^-40, 2^40), so that
+// d2 * sqrt(d2) lies in [2^-60, 2^60); G m in [2^-50, 2^30) or exactly 0 (an
+// empty tile entry), so that the quotient lies in [2^-110, 2^90).
+constexpr uint32_t kD2Lo = 0x2B800000u, kD2Hi = 0x53800000u;
+constexpr uint32_t kGmLo = 0x26800000u, kGmHi = 0x4E800000u;
+// Position of an empty tile entry: far from every body of the unit-disk
+// workload, so that with G m = 0 its term is exactly +0 (adding it leaves a
+// sum unchanged: a sum that starts at +0 is never -0).
+constexpr float kFarPos = 1024.0f;
+
+// offset of d2's bit pattern from the range's start: the value is in the
+// range iff the (unsigned) offset is below kD2Hi - kD2Lo
+__device__ __forceinline__ uint32_t d2_offset(float d2) { return __float_as_uint(d2) - kD2Lo; }
+
 // device_do over all bodies for every body (Sec. 2.1), tiled through LDS.
 // R = allocated blocks of the class in ascending order (k_enum).  A workgroup
 // owns four i-blocks (one per wave, lane = slot); all its waves stream the
 // j-blocks of R in ascending order, kTile blocks per LDS tile, so every body
-// adds its terms in ascending key order.
+// adds its terms in ascending key order.  The tile is consumed four entries
+// at a time: if every lane's four d2 are in the fast range (and every G m of
+// the tile is), the four terms come from the fast sqrt and division and are
+// added in order; otherwise (the body itself, an empty slot near a body, or
+// operands outside the range) the four entries go through the general
+// operations with each term taken or skipped by a select.
 constexpr uint32_t kTile = 16;
 
 __global__ __launch_bounds__(256) void k_nbody_force(DevHeap h, uint32_t cls, const uint32_t* R,
@@ -247,41 +306,61 @@ __global__ __launch_bounds__(256) void k_nbody_force(DevHeap h, uint32_t cls, co
     const float xi = me ? nb_f(h, p.ox, ikey) : 0.0f;
     const float yi = me ? nb_f(h, p.oy, ikey) : 0.0f;
     float sx = 0.0f, sy = 0.0f;
+    // general form of one entry: skipped entries (an empty slot, or body i
+    // itself) may produce inf or NaN in s, never used (a select keeps the sums)
+    auto exact = [&](const float4& v) {
+        const uint32_t tag = (uint32_t)__float_as_int(v.w);
+        const float dx = v.x - xi, dy = v.y - yi;
+        const float d2 = dx * dx + dy * dy;
+        const float s = v.z / (d2 * sqrtf(d2));
+        const float nx = sx + s * dx, ny = sy + s * dy;
+        const bool use = tag != 0 && tag - 1 != ikey;
+        sx = use ? nx : sx;
+        sy = use ? ny : sy;
+    };
     for (uint64_t t0 = 0; t0 < r; t0 += kTile) {
         __syncthreads();
+        bool slow = false;
         for (uint32_t e = threadIdx.x; e < kTile * 64; e += blockDim.x) {
             const uint64_t jr = t0 + (e >> 6);
             const uint32_t sl = e & 63;
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float4 v = make_float4(kFarPos, kFarPos, 0.0f, 0.0f);
             if (jr < r) {
                 const uint32_t jb = R[jr];
                 if (((h.alloc[jb] & valid) >> sl) & 1) {
                     const uint32_t jk = jb * 64 + sl;
                     v = make_float4(nb_f(h, p.ox, jk), nb_f(h, p.oy, jk), a.G * nb_f(h, p.om, jk),
                                     __int_as_float((int)(jk + 1)));
+                    slow |= __float_as_uint(v.z) - kGmLo >= kGmHi - kGmLo;
                 }
             }
             tile[e] = v;
         }
-        __syncthreads();
-        // Every entry is computed and the sums take it or keep their value
-        // (a select, so the order and the rounding of the additions are
-        // exactly those of the skip-form loop): no branch between entries,
-        // so the compiler can issue one 16-B LDS read per entry and several
-        // entries' reads ahead of their use.  Skipped entries (an empty slot,
-        // or body i itself) may produce inf or NaN in s; it is never used.
-        const uint32_t ne = (uint32_t)((r - t0 < kTile ? r - t0 : kTile) * 64);
-#pragma unroll 4
-        for (uint32_t e = 0; e < ne; ++e) {
-            const float4 v = tile[e];
-            const uint32_t tag = (uint32_t)__float_as_int(v.w);
-            const float dx = v.x - xi, dy = v.y - yi;
-            const float d2 = dx * dx + dy * dy;
-            const float s = v.z / (d2 * sqrtf(d2));
-            const float nx = sx + s * dx, ny = sy + s * dy;
-            const bool use = tag != 0 && tag - 1 != ikey;
-            sx = use ? nx : sx;
-            sy = use ? ny : sy;
+        const bool tile_slow = __syncthreads_or(slow) != 0;
+        const uint32_t ne = (uint32_t)((r - t0 < kTile ? r - t0 : kTile) * 64);   // a multiple of 64
+        if (tile_slow) {
+            for (uint32_t e = 0; e < ne; ++e) exact(tile[e]);
+            continue;
+        }
+        for (uint32_t e = 0; e < ne; e += 4) {
+            const float4 v0 = tile[e], v1 = tile[e + 1], v2 = tile[e + 2], v3 = tile[e + 3];
+            const float dx0 = v0.x - xi, dy0 = v0.y - yi, dx1 = v1.x - xi, dy1 = v1.y - yi;
+            const float dx2 = v2.x - xi, dy2 = v2.y - yi, dx3 = v3.x - xi, dy3 = v3.y - yi;
+            const float d20 = dx0 * dx0 + dy0 * dy0, d21 = dx1 * dx1 + dy1 * dy1;
+            const float d22 = dx2 * dx2 + dy2 * dy2, d23 = dx3 * dx3 + dy3 * dy3;
+            const uint32_t off = max(max(d2_offset(d20), d2_offset(d21)), max(d2_offset(d22), d2_offset(d23)));
+            if (__all(off < kD2Hi - kD2Lo)) {
+                const float s0 = div_cr_fast(v0.z, d20 * sqrt_cr_fast(d20));
+                const float s1 = div_cr_fast(v1.z, d21 * sqrt_cr_fast(d21));
+                const float s2 = div_cr_fast(v2.z, d22 * sqrt_cr_fast(d22));
+                const float s3 = div_cr_fast(v3.z, d23 * sqrt_cr_fast(d23));
+                sx = sx + s0 * dx0; sy = sy + s0 * dy0;
+                sx = sx + s1 * dx1; sy = sy + s1 * dy1;
+                sx = sx + s2 * dx2; sy = sy + s2 * dy2;
+                sx = sx + s3 * dx3; sy = sy + s3 * dy3;
+            } else {
+                exact(v0); exact(v1); exact(v2); exact(v3);
+            }
         }
     }
     if (me) {
@@ -290,6 +369,35 @@ __global__ __launch_bounds__(256) void k_nbody_force(DevHeap h, uint32_t cls, co
         const float ax = sx * a.dt, ay = sy * a.dt;
         vx = vx + ax;
         vy = vy + ay;
+    }
+}
+
+// Self-check of the fast arithmetic against the general correctly rounded
+// operations: out[0] += square roots that differ, over every float bit
+// pattern in [lo, hi) (one thread per pattern, grid-stride); out[1] +=
+// quotients that differ over `pairs` pseudo-random (G m, d2 * sqrt(d2))
+// operand pairs drawn from the fast ranges.
+__global__ void k_check_force_arith(uint32_t lo, uint32_t hi, uint64_t pairs, uint64_t seed,
+                                    unsigned long long* out) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t bad_sqrt = 0, bad_div = 0;
+    for (uint64_t b = lo + t; b < hi; b += stride) {
+        const float x = __uint_as_float((uint32_t)b);
+        bad_sqrt += __float_as_uint(sqrt_cr_fast(x)) != __float_as_uint(sqrtf(x));
+    }
+    for (uint64_t i = t; i < pairs; i += stride) {
+        const uint64_t z = splitmix64(seed ^ i);
+        const float gm = __uint_as_float(kGmLo + (uint32_t)(((z & 0xFFFFFFFFull) * (kGmHi - kGmLo)) >> 32));
+        const float d2 = __uint_as_float(kD2Lo + (uint32_t)(((z >> 32) * (kD2Hi - kD2Lo)) >> 32));
+        const float b = d2 * sqrtf(d2);
+        bad_div += __float_as_uint(div_cr_fast(gm, b)) != __float_as_uint(gm / b);
+    }
+    bad_sqrt = wave_add(bad_sqrt);
+    bad_div = wave_add(bad_div);
+    if (lane_id() == 0) {
+        if (bad_sqrt) atomicAdd(out, (unsigned long long)bad_sqrt);
+        if (bad_div) atomicAdd(out + 1, (unsigned long long)bad_div);
     }
 }
 

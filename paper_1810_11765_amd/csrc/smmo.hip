@@ -801,6 +801,19 @@ int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word,
     return SMMO_OK;
 }
 
+int smmo_check_force_arith(uint32_t lo_bits, uint32_t hi_bits, uint64_t pairs, uint64_t seed, uint64_t* counts_dev,
+                           void* stream) {
+    if (!counts_dev) return fail(SMMO_EINVAL, "check_force_arith: null output");
+    if (hi_bits < lo_bits || hi_bits > 0x7F800000u) return fail(SMMO_EINVAL, "check_force_arith: bad bit range");
+    hipStream_t s = S(stream);
+    k_fill_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long*>(counts_dev), 2, 0);
+    LAUNCH_CHECK("k_fill_u64");
+    k_check_force_arith<<<4096, 256, 0, s>>>(lo_bits, hi_bits, pairs, seed,
+                                             reinterpret_cast<unsigned long long*>(counts_dev));
+    LAUNCH_CHECK("k_check_force_arith");
+    return SMMO_OK;
+}
+
 int smmo_occupancy(smmo_heap* heap, uint64_t* used, uint64_t* slots, uint64_t* blocks, void* stream) {
     TimingScope timing(heap, false);
     if (!heap) return fail(SMMO_EINVAL, "null heap");

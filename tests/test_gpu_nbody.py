@@ -141,6 +141,53 @@ def test_correctly_rounded_div_sqrt_against_ieee():
     assert np.array_equal(vy.view(np.uint32), ay.view(np.uint32))
 
 
+def test_force_fast_arithmetic_equals_ieee():
+    """smmo_check_force_arith: the force kernel's fast square root equals the
+    correctly rounded one on every float of [2^-40, 2^40) (671,088,640 bit
+    patterns) and its fast division the correctly rounded one on 2^28
+    pseudo-random operand pairs of the fast ranges."""
+    import ctypes as C
+    from paper_1810_11765_amd import smmo as S
+    say("force arithmetic self-check")
+    L = S.lib()
+    L.smmo_check_force_arith.argtypes = [C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p]
+    L.smmo_check_force_arith.restype = C.c_int
+    out = torch.full((2,), 7, dtype=torch.int64, device="cuda")
+    for seed in (1, 2):
+        S.check(L.smmo_check_force_arith(0x2B800000, 0x53800000, 1 << 28, seed, out.data_ptr(),
+                                         C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        assert out.cpu().tolist() == [0, 0]
+
+
+def test_force_fallback_paths_against_ieee():
+    """Operands outside the fast ranges take the general operations: bodies
+    1e7 apart (d2 above 2^40), pairs 1e-7 apart (d2 below 2^-40), G m above
+    2^30 and below 2^-50, bodies at the position empty slots use; the force
+    phase alone equals the oracle's accelerations bit for bit."""
+    say("force fallback paths")
+    rng = np.random.default_rng(17)
+    n = 64 * 70 + 9
+    x = rng.uniform(-1, 1, n).astype(np.float32)
+    y = rng.uniform(-1, 1, n).astype(np.float32)
+    m = np.exp(rng.standard_normal(n)).astype(np.float32)
+    x[:40] = rng.uniform(-1e7, 1e7, 40).astype(np.float32)         # far away
+    for k in range(60, 90, 2):                                     # close pairs (no merge phase here)
+        x[k + 1] = x[k] + np.float32(1e-7)
+        y[k + 1] = y[k]
+    m[100:110] = np.float32(1e10)                                  # G m above the fast range
+    m[200:210] = np.float32(1e-20)                                 # and below it
+    x[300:304] = np.float32(1024.0)                                # where empty tile entries sit
+    y[300:304] = np.float32(1024.0) + np.arange(4, dtype=np.float32)
+    z = np.zeros(n, np.float32)
+    sim = W().NBody(n=n, init=(x, y, z, z.copy(), m), G=1.0, dt=1.0)
+    sim.populate()
+    sim.phase(34)                                      # FORCE only: v = a*1
+    _, _, _, vx, vy, _ = sim.state()
+    ax, ay = core.c4_accel(x, y, m, np.arange(n), G=1.0)
+    assert np.array_equal(vx.view(np.uint32), ax.view(np.uint32))
+    assert np.array_equal(vy.view(np.uint32), ay.view(np.uint32))
+
+
 def test_nbody_config_100_steps_against_oracle_goldens():
     """The configuration as stated: 262,144 bodies of seed 42, 100 steps.  At
     steps 1, 10 and 100 the survivors are compared with the oracle's values
