@@ -394,7 +394,8 @@ def batch_sub(torch, steps=200, count=256):
     base, t_base, grid_base = sv.run_batched(reqs, steps, arena, per_launch=1, graph=True)
     batched, t_batch, grid = sv.run_batched(reqs, steps, arena, per_launch=tuned["steps_per_launch"], graph=True,
                                             wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"])
-    served = sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"])
+    served = sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"],
+                      steps_per_tick=tuned["steps_per_launch"])
     same = all(
         all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], batched[r.rid][0])) and
         all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], base[r.rid][0])) and
@@ -415,6 +416,9 @@ def batch_sub(torch, steps=200, count=256):
             "served_p50_step_ms": round(float(np.percentile(lat, 50)), 4),
             "served_p99_step_ms": round(float(np.percentile(lat, 99)), 4),
             "served_max_admit_delay_s": round(float(served["admit_delay_s"].max()), 4),
+            "served_steps_per_launch": tuned["steps_per_launch"],
+            "served_busy_over_batched": round(served["busy_s"] / t_batch, 2),
+            "served_admission_ms_p50_p99": [round(float(np.percentile(served["admit_ms"], q)), 3) for q in (50, 99)],
             "identical_results": bool(same), "status": int(status)}
 
 

@@ -496,9 +496,11 @@ int smmo_batch_add_wator(smmo_batch* batch, smmo_heap* heap, const smmo_wator_ar
                          void* stream, uint32_t* slot_out);
 int smmo_batch_remove(smmo_batch* batch, uint32_t slot);
 /* Advance every instance by min(steps, its remaining steps).  Asynchronous,
- * no host synchronization and no memset (safe under stream capture) unless
- * the instance set changed since the last call, in which case the schedule
- * is uploaded first (synchronously). */
+ * no host synchronization and no memset.  If the instance set or grid changed
+ * since the last call, the schedule is uploaded first, in stream order from
+ * pinned staging (not under stream capture: capture with
+ * smmo_batch_capture_graph, which uploads before it captures).  Calls on one
+ * batch must use one stream at a time. */
 int smmo_batch_step(smmo_batch* batch, uint32_t steps, void* stream);
 /* Capture `launches` persistent-kernel launches of `steps_per_launch` steps
  * each (the work of that many smmo_batch_step calls) into a HIP graph and

@@ -29,32 +29,58 @@ struct BatchSched {         // host-written schedule
 };
 
 constexpr uint32_t kBarrierSpin = 1u << 24;
+constexpr uint32_t kBatchUnit = 8;                        // blocks per unit of work in a phase
+constexpr uint64_t kUnitMask = (1ull << kBatchUnit) - 1;
 
-// Barrier among the workgroups of one instance.  Arrival is a release (this
-// workgroup's stores of the phase become visible at agent scope); the wait
-// polls the counter with relaxed loads and acquires once, after the last
-// poll: on gfx950 an agent-scope acquire invalidates the XCD's L2, so an
-// acquire on every poll would evict what the other workgroups there are
-// working on, once per poll.
-__device__ inline void instance_barrier(uint32_t* cnt, uint32_t target, uint32_t* status) {
+// Barrier among the workgroups of one instance, a two-level tree: each
+// workgroup arrives at the counter of its group of kBarGroup workgroups (a
+// release: its stores of the phase become visible at agent scope); the last
+// arrival of a group acquires them and arrives at the instance's top counter;
+// the last of those opens the barrier by storing the barrier's number in a
+// word of its own, which every workgroup polls with relaxed loads and
+// back-off, then acquires once.  A single counter that every workgroup both
+// incremented and polled cost ~0.2 ms per barrier at ~400 workgroups (the
+// polls and increments of one line queue behind each other at the memory
+// side); here at most kBarGroup increments meet on a group line, and the
+// polled word changes once per barrier.  On gfx950 an agent-scope acquire
+// invalidates the XCD's L2, so only group leaders take one on arrival.
+// Layout of an instance's region (uint32 words, zeroed before each launch):
+// [0] top counter, [32] number of the last barrier opened, [64 + 32 g] the
+// counter of group g (each on its own 128-B line).
+constexpr uint32_t kBarGroup = 16;
+__host__ __device__ inline uint32_t bar_words(uint32_t grid) { return 64 + 32 * ((grid + kBarGroup - 1) / kBarGroup); }
+
+__device__ inline void instance_barrier(uint32_t* bar, uint32_t number, uint32_t rank, uint32_t nwg, uint32_t* status) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t g = rank / kBarGroup;
+        const uint32_t gsize = nwg - g * kBarGroup < kBarGroup ? nwg - g * kBarGroup : kBarGroup;
+        const uint32_t ngroups = (nwg + kBarGroup - 1) / kBarGroup;
+        const uint32_t old = __hip_atomic_fetch_add(&bar[64 + 32 * g], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == number * gsize) {                        // last of its group
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const uint32_t t = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (t + 1 == number * ngroups) {                    // last group: open the barrier
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(&bar[32], number, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         uint32_t spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < number) {
             if (++spins > kBarrierSpin) {
                 __hip_atomic_fetch_or(status, SMMO_STATUS_RETRY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
-            __builtin_amdgcn_s_sleep(1);
+            if (spins < 8) __builtin_amdgcn_s_sleep(1);        // back off after the first polls
+            else __builtin_amdgcn_s_sleep(4);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
 
-// One phase of one instance, spread over the instance's waves; units of 16
-// block bits of allocated[cls].  With `snap`, each visited block's iteration
+// One phase of one instance, spread over the instance's waves; units of
+// kBatchUnit block bits of allocated[cls].  With `snap`, each visited block's iteration
 // word is set from its allocation word after the method ran (the method of a
 // plan phase neither creates nor destroys objects of the class).
 template <class M>
@@ -63,19 +89,20 @@ __device__ inline void batch_phase(const DevHeap& h, uint32_t cls, const smmo_wa
     const uint32_t lane = lane_id();
     const uint64_t* l0 = bm_word(h, bm_allocated(cls), 0, 0);
     const uint64_t valid = ~h.cls_pad[cls];
-    const uint64_t nunits = h.level_words[0] * 4;
+    constexpr uint32_t kPerWord = 64 / kBatchUnit;
+    const uint64_t nunits = h.level_words[0] * kPerWord;
     const typename M::Prep prep = M::prepare(h, cls, a);
     for (uint64_t u = wave_rank; u < nunits; u += nwaves) {
-        const uint64_t w = u >> 2;
-        const uint32_t first = (uint32_t)(u & 3) * 16;
+        const uint64_t w = u / kPerWord;
+        const uint32_t first = (uint32_t)(u % kPerWord) * kBatchUnit;
         const uint64_t my_blk = (w << 6) + first + lane;
-        const bool mine = lane < 16 && my_blk < h.M;
+        const bool mine = lane < kBatchUnit && my_blk < h.M;
         uint64_t my_word = 0, word;
         if (!M::kSnapshot) {       // no block of the class appears during a plan phase
             if (mine) my_word = at_load(&h.alloc[my_blk]);
-            word = at_load(l0 + w) & (0xFFFFull << first);
+            word = at_load(l0 + w) & (kUnitMask << first);
         } else {
-            word = at_load(l0 + w) & (0xFFFFull << first);
+            word = at_load(l0 + w) & (kUnitMask << first);
             if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
         }
         while (word) {
@@ -92,7 +119,8 @@ __device__ inline void batch_phase(const DevHeap& h, uint32_t cls, const smmo_wa
 }
 
 __global__ __launch_bounds__(256) void k_batch_wator(BatchDesc* desc, BatchProg* prog, const BatchSched* sched,
-                                                      const int32_t* wg_inst, uint32_t* bar, uint32_t steps) {
+                                                      const int32_t* wg_inst, uint32_t* bars, uint32_t bar_stride,
+                                                      uint32_t steps) {
     const int32_t i = wg_inst[blockIdx.x];
     if (i < 0) return;                                            // idle workgroup (uniform)
     BatchDesc& D = desc[i];
@@ -103,17 +131,18 @@ __global__ __launch_bounds__(256) void k_batch_wator(BatchDesc* desc, BatchProg*
     const uint32_t wave_rank = r * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint32_t nwaves = S.wg_count * (blockDim.x >> 6);
     uint32_t nbar = 0;
+    uint32_t* bar = bars + (uint64_t)i * bar_stride;
     for (uint32_t s = 0; s < todo; ++s) {
         smmo_wator_args a = D.a;
         a.step = (int32_t)(done0 + s + 1);
         batch_phase<MFishPlan>(D.h, a.fish_cls, a, wave_rank, nwaves, true);
-        instance_barrier(&bar[i], ++nbar * S.wg_count, D.h.status);
+        instance_barrier(bar, ++nbar, r, S.wg_count, D.h.status);
         batch_phase<MFishMove>(D.h, a.fish_cls, a, wave_rank, nwaves, false);
-        instance_barrier(&bar[i], ++nbar * S.wg_count, D.h.status);
+        instance_barrier(bar, ++nbar, r, S.wg_count, D.h.status);
         batch_phase<MSharkPlan>(D.h, a.shark_cls, a, wave_rank, nwaves, true);
-        instance_barrier(&bar[i], ++nbar * S.wg_count, D.h.status);
+        instance_barrier(bar, ++nbar, r, S.wg_count, D.h.status);
         batch_phase<MSharkMove>(D.h, a.shark_cls, a, wave_rank, nwaves, false);
-        instance_barrier(&bar[i], ++nbar * S.wg_count, D.h.status);
+        instance_barrier(bar, ++nbar, r, S.wg_count, D.h.status);
     }
     if (r == 0 && threadIdx.x == 0) {
         prog[i].remaining -= todo;

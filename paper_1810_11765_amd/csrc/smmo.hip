@@ -996,6 +996,9 @@ struct smmo_batch {
     uint32_t* d_bar;
     std::vector<int> used;                      // slot in use
     std::vector<uint64_t> weight;               // grid cells of each slot
+    std::vector<uint32_t> cap;                  // most workgroups a slot's instance can use
+    uint8_t* h_stage = nullptr;                 // pinned staging of the schedule tables
+    hipEvent_t stage_done = nullptr;            // the last upload from the staging has completed
     bool dirty;
     uint64_t generation = 0;                    // bumped whenever the instance set or grid changes
 };
@@ -1094,7 +1097,7 @@ int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
     B->grid_max = B->grid = (uint32_t)cus * (uint32_t)per_cu;
     const uint64_t bytes = align_up(sizeof(BatchDesc) * max_inst, 256) + align_up(sizeof(BatchProg) * max_inst, 256) +
                            align_up(sizeof(BatchSched) * max_inst, 256) + align_up(4ull * B->grid_max, 256) +
-                           align_up(4ull * max_inst, 256);
+                           align_up(4ull * max_inst * bar_words(B->grid_max), 256);
     void* p = nullptr;
     int rc = smmo_arena_alloc(arena, bytes, &p);
     if (rc) { delete B; return rc; }
@@ -1107,6 +1110,23 @@ int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
     B->d_bar = reinterpret_cast<uint32_t*>(q);
     B->used.assign(max_inst, 0);
     B->weight.assign(max_inst, 0);
+    B->cap.assign(max_inst, 0);
+    {
+        void* hp = nullptr;
+        const uint64_t stage_bytes = sizeof(BatchSched) * max_inst + 4ull * B->grid_max;
+        if (hipHostMalloc(&hp, stage_bytes, hipHostMallocDefault) != hipSuccess || !hp) {
+            smmo_arena_free(arena, B->dev);
+            delete B;
+            return fail(SMMO_EHIP, "batch: pinned staging of %llu bytes", (unsigned long long)stage_bytes);
+        }
+        B->h_stage = static_cast<uint8_t*>(hp);
+        if (hipEventCreateWithFlags(&B->stage_done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(hp);
+            smmo_arena_free(arena, B->dev);
+            delete B;
+            return fail(SMMO_EHIP, "batch: event creation");
+        }
+    }
     B->dirty = true;
     std::vector<BatchProg> prog(max_inst, BatchProg{0, 0});
     HIP_TRY(hipMemcpy(B->d_prog, prog.data(), sizeof(BatchProg) * max_inst, hipMemcpyHostToDevice));
@@ -1116,6 +1136,11 @@ int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
 
 int smmo_batch_destroy(smmo_batch* B) {
     if (!B) return SMMO_OK;
+    if (B->stage_done) {
+        (void)hipEventSynchronize(B->stage_done);
+        (void)hipEventDestroy(B->stage_done);
+    }
+    if (B->h_stage) (void)hipHostFree(B->h_stage);
     smmo_arena_free(B->arena, B->dev);
     delete B;
     return SMMO_OK;
@@ -1141,6 +1166,8 @@ int smmo_batch_add_wator(smmo_batch* B, smmo_heap* heap, const smmo_wator_args* 
     HIP_TRY(hipStreamSynchronize(s));
     B->used[slot] = 1;
     B->weight[slot] = (uint64_t)args->width * (uint64_t)args->height;
+    // one wave per unit of the instance's heap (kBatchUnit blocks, batch.h) at most
+    B->cap[slot] = (uint32_t)std::max<uint64_t>(1, (heap->hdr.num_blocks + 4 * kBatchUnit - 1) / (4 * kBatchUnit));
     B->dirty = true;
     ++B->generation;
     *slot_out = slot;
@@ -1156,29 +1183,37 @@ int smmo_batch_remove(smmo_batch* B, uint32_t slot) {
     return SMMO_OK;
 }
 
-// Workgroups per instance proportional to its cells (at least one each).
+// Workgroups per instance proportional to its cells (at least one each), but
+// no more than it can use: every workgroup of an instance takes part in its
+// four barriers per step, and each arrival and departure writes back and
+// invalidates that XCD's L2, so idle workgroups cost time.  The tables are
+// uploaded in stream order from pinned staging (no host synchronization of
+// the stream); the staging is reused only once its previous upload is done.
 static int batch_schedule(smmo_batch* B, hipStream_t s) {
-    std::vector<int32_t> wg(B->grid, -1);
-    std::vector<BatchSched> sched(B->max_inst, BatchSched{0, 0});
+    HIP_TRY(hipEventSynchronize(B->stage_done));
+    BatchSched* sched = reinterpret_cast<BatchSched*>(B->h_stage);
+    int32_t* wg = reinterpret_cast<int32_t*>(B->h_stage + sizeof(BatchSched) * B->max_inst);
+    for (uint32_t i = 0; i < B->grid; ++i) wg[i] = -1;
     uint64_t total = 0;
     uint32_t n = 0;
-    for (uint32_t i = 0; i < B->max_inst; ++i)
+    for (uint32_t i = 0; i < B->max_inst; ++i) {
+        sched[i] = BatchSched{0, 0};
         if (B->used[i]) { total += B->weight[i]; ++n; }
+    }
     if (n > B->grid) return fail(SMMO_EINVAL, "batch: %u instances but only %u workgroups", n, B->grid);
     uint32_t next = 0;
-    uint32_t spare = B->grid - n;                          // beyond one each
+    const uint32_t spare = B->grid - n;                    // beyond one each
     for (uint32_t i = 0; i < B->max_inst; ++i) {
         if (!B->used[i]) continue;
-        uint32_t extra = total ? (uint32_t)((double)spare * (double)B->weight[i] / (double)total) : 0;
-        // cap by the instance's size: one workgroup per 4 L0 units is plenty
-        uint32_t cnt = 1 + extra;
+        const uint32_t extra = total ? (uint32_t)((double)spare * (double)B->weight[i] / (double)total) : 0;
+        const uint32_t cnt = std::min(1 + extra, std::max(1u, B->cap[i]));
         sched[i] = BatchSched{next, cnt};
         for (uint32_t k = 0; k < cnt; ++k) wg[next + k] = (int32_t)i;
         next += cnt;
     }
-    HIP_TRY(hipMemcpy(B->d_sched, sched.data(), sizeof(BatchSched) * B->max_inst, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(B->d_wg_inst, wg.data(), 4ull * B->grid, hipMemcpyHostToDevice));
-    (void)s;
+    HIP_TRY(hipMemcpyAsync(B->d_sched, sched, sizeof(BatchSched) * B->max_inst, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(B->d_wg_inst, wg, 4ull * B->grid, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(B->stage_done, s));
     B->dirty = false;
     return SMMO_OK;
 }
@@ -1186,17 +1221,17 @@ static int batch_schedule(smmo_batch* B, hipStream_t s) {
 // One persistent launch: the instance barrier counters are cleared by a
 // kernel (not a memset, so the pair can be captured and replayed).
 static int batch_launch(smmo_batch* B, uint32_t steps, hipStream_t s) {
-    k_fill_u64<<<grid_for((B->max_inst + 1) / 2, 256), 256, 0, s>>>(reinterpret_cast<unsigned long long*>(B->d_bar),
-                                                                     (B->max_inst + 1) / 2, 0);
+    const uint32_t stride = bar_words(B->grid_max);
+    const uint64_t bar_u64 = ((uint64_t)B->max_inst * stride + 1) / 2;
+    k_fill_u64<<<grid_for(bar_u64, 256), 256, 0, s>>>(reinterpret_cast<unsigned long long*>(B->d_bar), bar_u64, 0);
     LAUNCH_CHECK("k_fill_u64");
-    k_batch_wator<<<B->grid, 256, 0, s>>>(B->d_desc, B->d_prog, B->d_sched, B->d_wg_inst, B->d_bar, steps);
+    k_batch_wator<<<B->grid, 256, 0, s>>>(B->d_desc, B->d_prog, B->d_sched, B->d_wg_inst, B->d_bar, stride, steps);
     LAUNCH_CHECK("k_batch_wator");
     return SMMO_OK;
 }
 
 static int batch_prepare(smmo_batch* B, hipStream_t s) {
     if (!B->dirty) return SMMO_OK;
-    HIP_TRY(hipStreamSynchronize(s));
     return batch_schedule(B, s);
 }
 

@@ -48,8 +48,9 @@ def make_requests(seed: int = 42, count: int = 256, rate: float = 50.0, lo: int 
 
 
 def arena_bytes_for(reqs) -> int:
-    """Arena size that holds every request at once (plus batch tables)."""
-    tot = 1 << 22
+    """Arena size that holds every request at once (plus batch tables: the
+    persistent kernel's barrier words take ~8.5 KB per slot)."""
+    tot = (1 << 22) + 9 * 1024 * len(reqs)
     for r in reqs:
         n = r.side * r.side
         tot += S.heap_bytes(WaTor.CLASSES, wator_blocks(r.kind0)) + 16 * n + 4096
@@ -62,13 +63,17 @@ def instance_state(w: WaTor):
 
 
 class Fleet:
-    """A batch plus the instances it runs."""
+    """A batch plus the instances it runs.  The host counts every instance's
+    remaining steps itself (the batch kernel advances each by min(steps,
+    remaining)), so finding finished instances needs no device readback; the
+    device's own count is checked once, when an instance leaves."""
 
     def __init__(self, arena: S.Arena, max_instances: int = 256, lookups: int = 5):
         self.arena = arena
         self.batch = S.Batch(arena, max_instances)
         self.lookups = lookups              # active-block lookups r of every instance heap
         self.live = {}                      # slot -> (request, WaTor)
+        self.left = {}                      # slot -> steps still to run
 
     def admit(self, req: Request, steps: int, stream=None) -> bool:
         try:
@@ -81,14 +86,32 @@ class Fleet:
         w.populate(stream)
         slot = self.batch.add(w.heap, w.args, steps, stream)
         self.live[slot] = (req, w)
+        self.left[slot] = steps
         return True
+
+    def step(self, steps: int, stream=None) -> None:
+        self.batch.step(steps, stream)
+        self.advanced(steps)
+
+    def advanced(self, steps: int) -> None:
+        """Account for `steps` steps run on the batch (by step() or a graph replay)."""
+        for slot in self.left:
+            self.left[slot] = max(0, self.left[slot] - steps)
+
+    def finished(self) -> bool:
+        return any(v == 0 for v in self.left.values())
 
     def harvest(self, stream=None):
         """Finished instances: (request, state, status); their memory is released."""
         done = []
+        slots = [s for s in self.live if self.left[s] == 0]
+        if not slots:
+            return done
         rem = self.batch.remaining(stream)
-        for slot in [s for s in self.live if rem[s] == 0]:
+        for slot in slots:
+            assert rem[slot] == 0, f"slot {slot}: the device still counts {rem[slot]} steps"
             req, w = self.live.pop(slot)
+            del self.left[slot]
             done.append((req, instance_state(w), w.heap.status()))
             self.batch.remove(slot)
             w.release()
@@ -139,10 +162,11 @@ def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bo
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         g.close()
+        fleet.advanced(launches * per_launch)
     else:
         t0 = time.perf_counter()
         for _ in range(launches):
-            fleet.batch.step(per_launch)
+            fleet.step(per_launch)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
     grid = fleet.batch.grid()
@@ -153,38 +177,44 @@ def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bo
 
 
 def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instances: int = 256,
-          wg_per_cu: int = 0, lookups: int = 5):
-    """Continuous batching over arrivals (arrival times scaled by time_scale),
-    one persistent-kernel step per launch on wg_per_cu workgroups per CU
-    (0 = all that fit).
+          wg_per_cu: int = 0, lookups: int = 5, steps_per_tick: int = 10):
+    """Continuous batching over arrivals (arrival times scaled by time_scale):
+    between launches, arrived requests are admitted while the arena has room;
+    each launch advances every live instance by up to `steps_per_tick` steps
+    (one persistent-kernel launch on wg_per_cu workgroups per CU, 0 = all that
+    fit); finished instances leave and free their memory.
 
-    Returns dict with results per request, per instance-step latencies (ms),
-    wall seconds, busy seconds and admission delays.
-    """
-    fleet = Fleet(arena, max_instances, lookups=lookups)
+    Returns dict with results per request, per instance-step latencies (ms:
+    the launch's GPU time over its steps, one entry per live instance and
+    step), wall seconds, busy seconds (GPU time of the launches), admission
+    host times (ms, outside the latencies) and admission delays."""
+    fleet = Fleet(arena, max(1, min(max_instances, len(reqs))), lookups=lookups)
     fleet.batch.set_grid(wg_per_cu)
     pending = deque(sorted(reqs, key=lambda r: r.arrival))
-    lat, admit_delay, results = [], [], {}
+    lat, admit_delay, admit_ms, results = [], [], [], {}
     busy = 0.0
     t0 = time.perf_counter()
     while pending or fleet.live:
         now = time.perf_counter() - t0
         while pending and pending[0].arrival * time_scale <= now:
+            ta = time.perf_counter()
             if not fleet.admit(pending[0], steps):
                 if not fleet.live:
                     raise S.SmmoError(f"request {pending[0].rid} does not fit in the empty arena")
                 break                                   # wait until memory frees up
+            admit_ms.append((time.perf_counter() - ta) * 1e3)
             admit_delay.append(now - pending[0].arrival * time_scale)
             pending.popleft()
         if fleet.live:
+            k = min(steps_per_tick, min(fleet.left.values()))      # stop when the first instance ends
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
-            fleet.batch.step(1)
+            fleet.step(k)
             b.record()
             b.synchronize()
             ms = a.elapsed_time(b)
             busy += ms * 1e-3
-            lat.extend([ms] * len(fleet.live))
+            lat.extend([ms / k] * (len(fleet.live) * k))
             for req, st, status in fleet.harvest():
                 results[req.rid] = (st, status)
         elif pending:
@@ -192,4 +222,4 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
     wall = time.perf_counter() - t0
     fleet.close()
     return {"results": results, "latency_ms": np.array(lat), "wall_s": wall, "busy_s": busy,
-            "admit_delay_s": np.array(admit_delay)}
+            "admit_ms": np.array(admit_ms), "admit_delay_s": np.array(admit_delay)}

@@ -201,6 +201,7 @@ def test_captured_batch_graph_replayed_several_times_matches_oracle():
         say("replay", rep)
         g.launch(stream=stream)
         torch.cuda.synchronize()
+        fleet.advanced(5)
         for slot, (r, w) in fleet.live.items():
             kind, age, energy = w.state()
             ok, oa, oe = core.c3_run(r.kind0, r.side, r.side, r.seed, 5 * rep)
