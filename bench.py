@@ -283,6 +283,46 @@ def alloc_scaled_sub(torch):
     return res
 
 
+def alloc_partial_sub(torch):
+    """Allocation at scale with partial wave requests (contended reservations
+    in shared active blocks): 2^16 blocks of driver objects; in every block the
+    first L slots each create one object of a second class (one do-all,
+    SMMO_M_SPAWN), L = 1, 8, 32, so each wave asks for L slots and 64 / L
+    waves share a fresh active block; then every spawned object destroys
+    itself.  Atomics per object from a second run with the counters on."""
+    from paper_1810_11765_amd import smmo as S
+    D = 1 << 16
+    out = {"driver_blocks": D}
+    for L in (1, 8, 32):
+        row = {}
+        for counted in (False, True):
+            h = S.Heap([[4], [4]], D + (D * L + 63) // 64 + 1024)
+            h.parallel_new(0, D * 64, S.CTOR_NONE)
+            if counted:
+                h.set_tuning(S.TUNE_STATS, 5, 0)
+            torch.cuda.synchronize()
+            tm = Timer(torch)
+            tm.run("spawn", lambda: h.parallel_do(0, S.M_SPAWN, S.SpawnArgs(1, L)))
+            torch.cuda.synchronize()
+            live = h.live_count(1)
+            tm.run("destroy", lambda: h.parallel_do(1, S.M_DESTROY_ALL))
+            torch.cuda.synchronize()
+            if counted:
+                st = h.stats()
+                row["atomic_ors_per_object"] = round(st["reserve_atomic"] / max(st["alloc_obj"], 1), 4)
+                row["reserve_fail_per_object"] = round(st["reserve_fail"] / max(st["alloc_obj"], 1), 4)
+                row["blocks_initialized"] = st["block_init"]
+            else:
+                a, d = tm.ms("spawn")[0], tm.ms("destroy")[0]
+                row.update({"objects": live, "spawn_ms": round(a, 4), "destroy_ms": round(d, 4),
+                            "alloc_mobj_s": round(live / (a * 1e-3) / 1e6, 1),
+                            "destroy_mobj_s": round(live / (d * 1e-3) / 1e6, 1),
+                            "left_after_destroy": h.live_count(1), "status": h.status()})
+            h.close()
+        out[f"lanes_{L}"] = row
+    return out
+
+
 def nbody_sub(torch, workloads, steps=2):
     """N-body with merging at 262,144 bodies: per-phase event times of
     `steps` steps after one warm-up step; interactions/s of the all-pairs
@@ -326,6 +366,17 @@ def sweep_sub(torch, nblocks):
     torch.cuda.synchronize()
     ms = sorted(tm.ms("sweep"))[len(tm.ms("sweep")) // 2]
     gbs = 12.0 * n / (ms * 1e-3) / 1e9
+    # the same sweep through the generic do-all kernel (one wave per block,
+    # lane = slot): what a method without a streaming form gets
+    gen_args = S.AxpyArgs(0.5, 1, 2, 0)
+    for _ in range(2):
+        h.parallel_do(0, S.M_AXPY_GENERIC, gen_args)
+    tmg = Timer(torch)
+    for _ in range(10):
+        tmg.run("g", lambda: h.parallel_do(0, S.M_AXPY_GENERIC, gen_args))
+    torch.cuda.synchronize()
+    ms_gen = sorted(tmg.ms("g"))[5]
+    gbs_gen = 12.0 * n / (ms_gen * 1e-3) / 1e9
     # about half of the objects destroyed at random (fixed seed): the sweep
     # still streams whole block segments, so its algorithmic rate (live bytes
     # only) shows what fragmentation costs
@@ -368,6 +419,9 @@ def sweep_sub(torch, nblocks):
             "plain_array_reference_gbs": round(ref_gbs, 1),
             "fraction_of_plain_array_reference": round(gbs / ref_gbs, 3),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "generic_doall": {"kernel": "k_doall<MAxpy>", "ms_median": round(ms_gen, 4), "gbs": round(gbs_gen, 1),
+                              "hbm_frac": round(gbs_gen / HBM_PEAK_GBS, 4),
+                              "fraction_of_streaming": round(gbs_gen / gbs, 3)},
             "half_fill": {"live_objects": live_half, "ms_median": round(ms_half, 4),
                           "algorithmic_gbs": round(12.0 * live_half / (ms_half * 1e-3) / 1e9, 1),
                           "field_segment_gbs": round(12.0 * n / (ms_half * 1e-3) / 1e9, 1)},
@@ -434,8 +488,8 @@ def _wator_same(w, oracle_state):
                 np.array_equal(energy[kind == 2], oe[ok == 2]))
 
 
-ABLATION_VARIANTS = [("default", 0, 5), ("noshift", 1, 5), ("nocoal", 2, 5), ("nocoal-noshift", 3, 5),
-                     ("r1", 0, 1), ("r2", 0, 2), ("r3", 0, 3), ("r5", 0, 5), ("r8", 0, 8)]
+ABLATION_VARIANTS = [("default", 0, 5), ("rotated-start", 64, 5), ("noshift", 1, 5), ("nocoal", 2, 5),
+                     ("nocoal-noshift", 3, 5), ("r1", 0, 1), ("r2", 0, 2), ("r3", 0, 3), ("r5", 0, 5), ("r8", 0, 8)]
 
 
 ABLATION_BLOCKS = 65536
@@ -443,7 +497,8 @@ ABLATION_BLOCKS = 65536
 
 def ablation_suite(torch, workloads, steps):
     """Predator-prey 1024 x 1024 (seed 42) under each allocator variant of
-    Sec. 6.3: rotation off (noshift), request coalescing off (nocoal), both,
+    Sec. 6.3: the paper's rotated-start search (rotated-start), rotation off
+    (noshift), request coalescing off (nocoal), both,
     and r = 1..8 active-block lookups.  Per variant: step time (events around
     each step), fragmentation F every 10 steps (occupancy query, outside the
     timed spans) and whether the final state equals the oracle's.  The heap
@@ -782,6 +837,8 @@ def main():
         out["atomic_reference"] = atomic_ceiling(torch)
         _progress("alloc at scale")
         out["alloc_scaled"] = alloc_scaled_sub(torch)
+        _progress("alloc at scale, partial requests")
+        out["alloc_scaled_partial"] = alloc_partial_sub(torch)
         _progress("sweep")
         out["sweep"] = sweep_sub(torch, args.sweep_blocks)
         _progress("n-body")

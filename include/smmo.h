@@ -146,6 +146,9 @@ enum smmo_counter {
 #define SMMO_TUNE_FORCE_FAIL 8u     /* try_find_set fails force_fail_ppm / 1e6 of the time */
 #define SMMO_TUNE_SLOW_PICK 16u     /* pause ~20 us between picking an active block and
                                        reserving in it (widens the race window of App. A.3) */
+#define SMMO_TUNE_ROTATED_START 64u /* bitmap lookups use the paper's rotated find-first-set
+                                       (start at a wave- and retry-dependent bit) instead of
+                                       picking one of the word's set bits uniformly */
 #define SMMO_TUNE_FLAT_ENUM 32u     /* do-all, snapshot and live count scan every level-0
                                        word even in big heaps (no level-1 skip) */
 
@@ -224,6 +227,11 @@ typedef struct smmo_ctor_none {
 #define SMMO_M_MIX 4u               /* two-class churn (test method)  (smmo_mix_args)   */
 #define SMMO_M_STRESS 5u            /* alloc/destroy storm (test)     (smmo_stress_args) */
 #define SMMO_M_CHURN_API 6u         /* SMMO_M_CHURN written against smmo_device.h only      */
+#define SMMO_M_SPAWN 8u             /* lanes < a.lanes of every block each create one object of
+                                       class a.cls, fields untouched (smmo_spawn_args): partial
+                                       wave requests sharing active blocks */
+#define SMMO_M_AXPY_GENERIC 7u      /* SMMO_M_AXPY through the generic do-all kernel (one
+                                       wave per block, lane = slot), not the streaming one */
 #define SMMO_M_LIFE_PLAN 10u        /* Cell: next state, B3/S23       (smmo_life_args)  */
 #define SMMO_M_LIFE_AGENT 11u       /* Agent: die or age              (smmo_life_args)  */
 #define SMMO_M_LIFE_COMMIT 12u      /* Cell: birth of agents, commit  (smmo_life_args)  */
@@ -245,6 +253,9 @@ typedef struct smmo_axpy_args { float a; uint32_t fx; uint32_t fy; uint32_t pad;
 /* Test method: atomically increments visits[field0 (int32)]. */
 typedef struct smmo_visit_args { uint32_t* visits; } smmo_visit_args;
 
+/* SMMO_M_SPAWN: objects of class `cls` created by the first `lanes` (1..64)
+ * slots of every visited block that hold a live object. */
+typedef struct smmo_spawn_args { uint32_t cls; uint32_t lanes; } smmo_spawn_args;
 /* Alloc microbench round `round` on class {int32 id, f32 x, f32 v}: each
  * object with splitmix64(seed ^ id ^ round) odd destroys itself and allocates
  * a replacement id' = ((round+1) << 18) | (id & 0x3FFFF) with

@@ -59,9 +59,11 @@ __device__ inline void instance_barrier(uint32_t* bar, uint32_t number, uint32_t
         const uint32_t old = __hip_atomic_fetch_add(&bar[64 + 32 * g], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (old + 1 == number * gsize) {                        // last of its group
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const uint32_t t = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            // an instance of one group opens the barrier at once
+            const uint32_t t =
+                ngroups == 1 ? number - 1 : __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             if (t + 1 == number * ngroups) {                    // last group: open the barrier
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (ngroups > 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __hip_atomic_store(&bar[32], number, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
         }

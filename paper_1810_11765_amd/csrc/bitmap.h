@@ -92,6 +92,20 @@ __device__ inline uint32_t pick_set_bit(uint64_t w, uint32_t r) {
     return nth_set_bit(w, (uint32_t)(((uint64_t)r * popc64(w)) >> 32));
 }
 
+// The paper's spreading (Sec. 4.2): the find-first-set starts at a bit that
+// depends on the wave and the retry (the word rotated right by r & 63), so
+// that waves spread over a word's set bits (SMMO_TUNE_ROTATED_START).
+__device__ inline uint32_t pick_rotated(uint64_t w, uint32_t r) {
+    const uint32_t rot = r & 63;
+    return (ctz64(rotr64(w, rot)) + rot) & 63;
+}
+// the set bit of w (w != 0) a lookup takes, by the heap's tuning
+__device__ inline uint32_t pick_bit(const DevHeap& h, uint64_t w, uint32_t r) {
+    if (h.tune & SMMO_TUNE_NO_ROTATE) return ctz64(w);
+    if (h.tune & SMMO_TUNE_ROTATED_START) return pick_rotated(w, r);
+    return pick_set_bit(w, r);
+}
+
 // try_find_set() (Alg. 4), top-down from the single top word.  Where the
 // paper rotates the start of each level's find-first-set (Sec. 4.2), this
 // picks one of the word's set bits uniformly: the same spreading of waves
@@ -104,13 +118,11 @@ __device__ inline uint64_t bm_try_find_set(const DevHeap& h, uint32_t b, uint64_
     if (h.tune & SMMO_TUNE_FORCE_FAIL) {
         if ((uint32_t)(splitmix64(seed) % 1000000u) < h.force_fail_ppm) return kFail;
     }
-    const bool rotate = !(h.tune & SMMO_TUNE_NO_ROTATE);
     uint64_t idx = 0;
     for (int l = (int)h.nlevels - 1; l >= 0; --l) {
         const uint64_t w = w_load(bm_word(h, b, (uint32_t)l, idx));
         if (!w) return kFail;
-        const uint32_t bit = rotate ? pick_set_bit(w, (uint32_t)(seed >> (6 * l))) : ctz64(w);
-        idx = (idx << 6) | bit;
+        idx = (idx << 6) | pick_bit(h, w, (uint32_t)(seed >> (6 * l)));
     }
     return idx;
 }
@@ -133,7 +145,7 @@ __device__ inline uint64_t bm_try_find_set_dense(const DevHeap& h, uint32_t b, u
         const uint64_t nz = ballot(wl != 0);
         if (nz) {
             const uint32_t i = nz == 3 ? (uint32_t)(seed >> 63) : ctz64(nz);
-            return (readlane64(j, i) << 6) | pick_set_bit(readlane64(wl, i), (uint32_t)seed);
+            return (readlane64(j, i) << 6) | pick_bit(h, readlane64(wl, i), (uint32_t)seed);
         }
     }
     return bm_try_find_set(h, b, seed);

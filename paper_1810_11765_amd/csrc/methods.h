@@ -13,7 +13,8 @@
 
 namespace smmo {
 
-// y += a*x on two float32 fields.
+// y += a*x on two float32 fields, through the generic do-all (SMMO_M_AXPY_GENERIC;
+// SMMO_M_AXPY runs the streaming kernel below).
 struct MAxpy {
     using Args = smmo_axpy_args;
     static constexpr bool kSnapshot = false;
@@ -112,6 +113,20 @@ struct MDestroyAll {
     __device__ static Prep prepare(const DevHeap&, uint32_t, const Args&) { return {}; }
     __device__ __forceinline__ static void run(const Obj& o, const Prep&, const Args&) {
         wave_destroy_self(o.h, o.cls, o.bid, o.live);
+    }
+};
+
+// Allocation at scale with partial wave requests: the first a.lanes slots of
+// every block each create one object of class a.cls (memory untouched), so
+// each wave asks for at most a.lanes slots and several waves share an
+// active block.
+struct MSpawn {
+    using Args = smmo_spawn_args;
+    static constexpr bool kSnapshot = false;
+    struct Prep {};
+    __device__ static Prep prepare(const DevHeap&, uint32_t, const Args&) { return {}; }
+    __device__ __forceinline__ static void run(const Obj& o, const Prep&, const Args& a) {
+        (void)o.alloc(a.cls, o.live && o.lane < a.lanes);
     }
 };
 

@@ -677,7 +677,28 @@ static int parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const 
             }
             return SMMO_OK;
         }
+        case SMMO_M_AXPY_GENERIC: {
+            smmo_axpy_args a;
+            rc = unpack_args(a, args, args_bytes, "axpy");
+            if (rc) return rc;
+            if (a.fx >= heap->hdr.nfields[cls] || a.fy >= heap->hdr.nfields[cls] ||
+                heap->hdr.field_bytes[cls][a.fx] != 4 || heap->hdr.field_bytes[cls][a.fy] != 4)
+                return fail(SMMO_EINVAL, "axpy: fields must be 4-byte fields of the class");
+            return launch_doall<MAxpy>(heap, cls, args, args_bytes, s, from_snapshot);
+        }
         case SMMO_M_DESTROY_ALL: return launch_doall<MDestroyAll>(heap, cls, nullptr, 0, s, from_snapshot);
+        case SMMO_M_SPAWN: {
+            smmo_spawn_args a;
+            rc = unpack_args(a, args, args_bytes, "spawn");
+            if (rc) return rc;
+            uint32_t cl[SMMO_MAX_CLASSES];
+            const uint32_t n = subtree(heap, cls, cl);
+            bool other = a.cls < heap->hdr.ncls;
+            for (uint32_t i = 0; i < n; ++i) other = other && a.cls != cl[i];
+            if (!other || a.lanes < 1 || a.lanes > 64)
+                return fail(SMMO_EINVAL, "spawn: a class outside the do-all's, lanes 1..64");
+            return launch_doall<MSpawn>(heap, cls, args, args_bytes, s, from_snapshot);
+        }
         case SMMO_M_VISIT: return launch_doall<MVisit>(heap, cls, args, args_bytes, s, from_snapshot);
         case SMMO_M_CHURN: return launch_doall<MChurn>(heap, cls, args, args_bytes, s, from_snapshot);
         case SMMO_M_CHURN_API: {

@@ -28,6 +28,8 @@ M_VISIT = 2
 M_CHURN = 3
 M_MIX = 4
 M_CHURN_API = 6
+M_AXPY_GENERIC = 7
+M_SPAWN = 8
 M_LIFE_PLAN = 10
 M_LIFE_AGENT = 11
 M_LIFE_COMMIT = 12
@@ -45,6 +47,7 @@ TUNE_NO_COALESCE = 2
 TUNE_STATS = 4
 TUNE_FORCE_FAIL = 8
 TUNE_FLAT_ENUM = 32
+TUNE_ROTATED_START = 64
 COUNTERS = ["alloc_obj", "free_obj", "block_init", "block_free", "inval_rollback", "type_rollback",
             "find_fail", "reserve_fail", "spin", "reserve_atomic", "guard_alloc", "guard_spin", "guard_inval",
             "oom"]
@@ -78,6 +81,10 @@ class CtorArrays(C.Structure):
 
 class AxpyArgs(C.Structure):
     _fields_ = [("a", C.c_float), ("fx", C.c_uint32), ("fy", C.c_uint32), ("pad", C.c_uint32)]
+
+
+class SpawnArgs(C.Structure):
+    _fields_ = [("cls", C.c_uint32), ("lanes", C.c_uint32)]
 
 
 class VisitArgs(C.Structure):

@@ -63,7 +63,7 @@ def test_wator_big_heap_parity(flat):
 
 
 VARIANTS = [("default", 0, 5), ("noshift", 1, 5), ("nocoal", 2, 5), ("nocoal-noshift", 3, 5),
-            ("r1", 0, 1), ("r2", 0, 2), ("r3", 0, 3), ("r8", 0, 8)]
+            ("r1", 0, 1), ("r2", 0, 2), ("r3", 0, 3), ("r8", 0, 8), ("rotated-start", 64, 5)]
 
 
 @pytest.mark.parametrize("name,flags,lookups", VARIANTS, ids=[v[0] for v in VARIANTS])
@@ -225,6 +225,15 @@ def test_launch_shapes_do_not_change_results(launch):
     for _ in range(3):
         want = want + np.float32(0.5) * xs
     assert np.array_equal(v, want)
+    # the same sweep through the generic do-all kernel, after destroying a
+    # third of the objects (holes in blocks)
+    refs = torch.from_numpy(h.dump_refs(0).astype(np.int64)[::3].copy()).cuda()
+    h.parallel_destroy(refs, refs.numel(), 1)
+    h.parallel_do(0, S_.M_AXPY_GENERIC, S_.AxpyArgs(0.5, 1, 2, 0))
+    ids, xv, v = h.dump_objects(0, [np.int32, np.float32, np.float32])
+    keep = np.ones(n, dtype=bool)
+    keep[::3] = False
+    assert np.array_equal(v, (want + np.float32(0.5) * xs)[keep])
 
 
 def test_launch_shape_rejects_out_of_range():
@@ -293,3 +302,22 @@ def test_timing_request_is_dropped_by_other_calls_and_taken_by_the_sweep():
     torch.cuda.synchronize()
     own, around = a2.elapsed_time(b2), o1.elapsed_time(o2)
     assert 0.0 < own <= around + 1e-3, (own, around)
+
+
+@pytest.mark.parametrize("lanes", [1, 8, 37, 64])
+def test_spawn_partial_requests_create_exactly_the_requested_objects(lanes):
+    """SMMO_M_SPAWN: the first `lanes` slots of every driver block each create
+    one object (partial wave requests sharing active blocks): exactly that
+    many objects exist afterwards, in a consistent heap, and destroy-all
+    removes them all."""
+    say("spawn", lanes)
+    S_ = S()
+    D = 300
+    n = D * 64 - 20                                   # a partial last block
+    h = S_.Heap([[4], [4]], D + (D * lanes + 63) // 64 + 16)
+    h.parallel_new(0, n, S_.CTOR_ZERO)
+    h.parallel_do(0, S_.M_SPAWN, S_.SpawnArgs(1, lanes))
+    want = (D - 1) * lanes + min(lanes, 64 - 20)
+    s = check_heap(h, expect_live=[n, want])
+    h.parallel_do(1, S_.M_DESTROY_ALL)
+    check_heap(h, expect_live=[n, 0])
