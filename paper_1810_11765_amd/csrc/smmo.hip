@@ -38,6 +38,14 @@ struct smmo_heap {
     hipEvent_t time_start = nullptr, time_stop = nullptr;   // smmo_time_next_doall, pending
     hipEvent_t armed_start = nullptr, armed_stop = nullptr; // taken by the current do-all call
     uint8_t* stage = nullptr;   // scratch of the current call when not the heap's own (static-scratch calls)
+    // The class whose block list the heap's scratch holds and is still
+    // current (-1: none): a do-all whose method creates and destroys nothing
+    // leaves every class's blocks as they were, so the next list of the same
+    // class is the same list.  Every call that may change blocks, or write
+    // the scratch list, resets it; a heap in a batch (changed by the batch
+    // kernel behind the host's back) never caches.
+    int32_t list_cls = -1;
+    bool in_batch = false;
 };
 
 // Static device scratch of smmo_parallel_do_static_scratch (see below):
@@ -275,12 +283,27 @@ bool build_block_list(smmo_heap* H, uint32_t cls, hipStream_t s, int* rc) {
     *rc = SMMO_OK;
     if (H->hdr.nlevels < 2 || H->hdr.level_words[0] < H->launch.list_min_words || (H->dev.tune & SMMO_TUNE_FLAT_ENUM))
         return false;
+    if (!H->stage && !H->in_batch && H->list_cls == (int32_t)cls) return true;   // still current
     unsigned long long* cnt = scratch_counter(H, 3);
     k_fill_u64<<<1, 64, 0, s>>>(cnt, 1, 0);
     if (hipGetLastError() != hipSuccess) { *rc = fail(SMMO_EHIP, "k_fill_u64 launch"); return false; }
     k_enum_blocks<<<grid_for(H->hdr.level_words[1], 4), 256, 0, s>>>(H->dev, bm_allocated(cls), scratch_R(H), cnt);
     if (hipGetLastError() != hipSuccess) { *rc = fail(SMMO_EHIP, "k_enum_blocks launch"); return false; }
+    H->list_cls = H->stage ? -1 : (int32_t)cls;
     return true;
+}
+
+// Methods that create and destroy no object (and do not write the scratch
+// list): a do-all of one of them keeps the cached block list.
+bool method_keeps_blocks(uint32_t method_id) {
+    switch (method_id) {
+        case SMMO_M_AXPY: case SMMO_M_AXPY_GENERIC: case SMMO_M_VISIT: case SMMO_M_LIFE_PLAN:
+        case SMMO_M_WATOR_FISH_PLAN: case SMMO_M_WATOR_SHARK_PLAN: case SMMO_M_NBODY_INSERT:
+        case SMMO_M_NBODY_PAIRS: case SMMO_M_NBODY_RESOLVE: case SMMO_M_NBODY_MOVE:
+            return true;
+        default:
+            return false;
+    }
 }
 
 // grid of the list-form thread-per-block passes: at most 32 waves per CU,
@@ -551,6 +574,7 @@ int smmo_heap_destroy(smmo_heap* heap) {
 
 int smmo_heap_reset(smmo_heap* heap, void* stream) {
     TimingScope timing(heap, false);
+    if (heap) heap->list_cls = -1;             // blocks (or the scratch list) change
     if (!heap) return fail(SMMO_EINVAL, "null heap");
     return init_device(heap, S(stream));
 }
@@ -599,6 +623,7 @@ int smmo_set_tuning(smmo_heap* heap, uint32_t flags, uint32_t lookups, uint32_t 
 int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_id, const void* args,
                       uint64_t args_bytes, void* stream) {
     TimingScope timing(heap, false);
+    if (heap) heap->list_cls = -1;             // blocks (or the scratch list) change
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     if (n == 0) return SMMO_OK;
@@ -613,6 +638,7 @@ int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_i
 int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32_t per_thread, uint32_t ctor_id,
                         const void* args, uint64_t args_bytes, void* stream) {
     TimingScope timing(heap, false);
+    if (heap) heap->list_cls = -1;             // blocks (or the scratch list) change
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     if (nthreads == 0 || per_thread == 0) return SMMO_OK;
@@ -630,6 +656,7 @@ int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32
 int smmo_parallel_destroy(smmo_heap* heap, const uint64_t* refs, uint64_t nthreads, uint32_t per_thread,
                           void* stream) {
     TimingScope timing(heap, false);
+    if (heap) heap->list_cls = -1;             // blocks (or the scratch list) change
     if (!heap) return fail(SMMO_EINVAL, "null heap");
     if (nthreads == 0 || per_thread == 0) return SMMO_OK;
     if (!refs) return fail(SMMO_EINVAL, "null refs");
@@ -746,14 +773,22 @@ static int parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const 
     }
 }
 
+// a do-all call, then the block-list cache kept or dropped by its method
+static int parallel_do_call(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
+                            uint64_t args_bytes, void* stream, bool from_snapshot) {
+    const int rc = parallel_do(heap, cls, method_id, args, args_bytes, stream, from_snapshot);
+    if (heap && !method_keeps_blocks(method_id)) heap->list_cls = -1;
+    return rc;
+}
+
 int smmo_parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args, uint64_t args_bytes,
                      void* stream) {
-    return parallel_do(heap, cls, method_id, args, args_bytes, stream, false);
+    return parallel_do_call(heap, cls, method_id, args, args_bytes, stream, false);
 }
 
 int smmo_parallel_do_snapshot(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
                               uint64_t args_bytes, void* stream) {
-    return parallel_do(heap, cls, method_id, args, args_bytes, stream, true);
+    return parallel_do_call(heap, cls, method_id, args, args_bytes, stream, true);
 }
 
 int smmo_parallel_do_static_scratch(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
@@ -766,7 +801,7 @@ int smmo_parallel_do_static_scratch(smmo_heap* heap, uint32_t cls, uint32_t meth
     int rc = static_scratch(&p);
     if (rc) return rc;
     StageScope stage(heap, p);
-    return parallel_do(heap, cls, method_id, args, args_bytes, stream, false);
+    return parallel_do_call(heap, cls, method_id, args, args_bytes, stream, false);
 }
 
 int smmo_time_next_doall(smmo_heap* heap, void* start_event, void* stop_event) {
@@ -1185,6 +1220,8 @@ int smmo_batch_add_wator(smmo_batch* B, smmo_heap* heap, const smmo_wator_args* 
     HIP_TRY(hipMemcpyAsync(&B->d_desc[slot], &d, sizeof d, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(&B->d_prog[slot], &pr, sizeof pr, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
+    heap->in_batch = true;                      // the batch kernel changes its blocks from now on
+    heap->list_cls = -1;
     B->used[slot] = 1;
     B->weight[slot] = (uint64_t)args->width * (uint64_t)args->height;
     // one wave per unit of the instance's heap (kBatchUnit blocks, batch.h) at most
