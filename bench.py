@@ -442,14 +442,18 @@ def batch_sub(torch, steps=200, count=256):
     inst_steps = count * steps
     # launch shape found by the autotuner for this workload on this device
     # (bench.py --suite autotune), if the package holds one
-    tuned = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5}
+    tuned = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5, "block_objects": 64}
     tuned.update(tune.load(TUNED_LAUNCH, "predator-prey batched %d instances %d steps" % (count, steps)) or {})
+    if tuned["block_objects"] != 64:
+        del arena
+        arena = S.Arena(max(sv.arena_bytes_for(reqs, b) for b in (64, tuned["block_objects"])))
     plain, t_plain = sv.run_plain(reqs, steps, arena)
     base, t_base, grid_base = sv.run_batched(reqs, steps, arena, per_launch=1, graph=True)
     batched, t_batch, grid = sv.run_batched(reqs, steps, arena, per_launch=tuned["steps_per_launch"], graph=True,
-                                            wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"])
+                                            wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"],
+                                            block_objects=tuned["block_objects"])
     served = sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"],
-                      steps_per_tick=tuned["steps_per_launch"])
+                      steps_per_tick=tuned["steps_per_launch"], block_objects=tuned["block_objects"])
     same = all(
         all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], batched[r.rid][0])) and
         all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], base[r.rid][0])) and
@@ -639,37 +643,71 @@ def heap_size_suite(torch, workloads, steps):
 
 
 def autotune_suite(torch, workloads, cache):
-    """The autotuner (paper_1810_11765_amd/tune.py) on three workloads:
+    """The autotuner (paper_1810_11765_amd/tune.py) on four workloads:
     the batched predator-prey form of config 5 (workgroups per CU of the
-    persistent kernel, steps per launch, active-block lookups r), the
-    Life-like step (r, do-all grid cap and unit count) and the 2^21-block
-    sweep (grid and blocks in flight).  Every
-    candidate's result is compared with the default shape's."""
+    persistent kernel, steps per launch, active-block lookups r, objects
+    per block), predator-prey 1024 x 1024 with per-phase launches (objects
+    per block, r, do-all grid cap and unit count), the Life-like step (r,
+    do-all grid cap and unit count) and the 2^21-block sweep (grid and
+    blocks in flight).  Every candidate's result is compared with the
+    default shape's."""
     import numpy as np
     from paper_1810_11765_amd import serve as sv
     from paper_1810_11765_amd import smmo as S
     from paper_1810_11765_amd import tune
     out = {"arch": tune.device_arch()}
 
-    # batched predator-prey (config 5: 256 instances x 200 steps), graph replay
+    # batched predator-prey (config 5: 256 instances x 200 steps), graph replay;
+    # objects per block of the smallest class is a layout knob (the bitmap
+    # fan-out stays 64: one bit per lane of a 64-wide wavefront)
     reqs = sv.make_requests(seed=42, count=256)
-    arena = S.Arena(sv.arena_bytes_for(reqs))
+    arena = S.Arena(max(sv.arena_bytes_for(reqs, b) for b in (64, 32)))
 
     def batched(cfg):
         _progress("autotune batched", cfg)
         res, dt, grid = sv.run_batched(reqs, 200, arena, per_launch=cfg["steps_per_launch"], graph=True,
-                                       wg_per_cu=cfg["wg_per_cu"], lookups=cfg["lookups"])
+                                       wg_per_cu=cfg["wg_per_cu"], lookups=cfg["lookups"],
+                                       block_objects=cfg["block_objects"])
         return dt, res
 
     def same_states(a, b):
         return all(all(np.array_equal(x, y) for x, y in zip(a[k][0], b[k][0])) and a[k][1] == b[k][1] == 0
                    for k in a)
     rec = tune.search(batched, {"wg_per_cu": [0, 1, 2, 3], "steps_per_launch": [1, 2, 5, 10],
-                                "lookups": [5, 3, 8, 12]}, reps=2, equal=same_states)
+                                "lookups": [5, 3, 8, 12], "block_objects": [64, 32]}, reps=2, equal=same_states)
     tune.save(cache, "predator-prey batched 256 instances 200 steps", rec)
     out["batched"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}
     out["batched"]["rejected"] = sum(not t["same_result"] for t in rec["trials"])
     del arena
+
+    # predator-prey 1024 x 1024 (config 3), plain per-phase launches, 100 steps
+    kind0 = workloads.inputs.wator_initial(42, 1024, 1024, 0.20, 0.05)
+
+    def wator(cfg):
+        _progress("autotune predator-prey", cfg)
+        b = cfg["block_objects"]
+        w = workloads.WaTor(seed=42, width=1024, height=1024, kind0=kind0, num_blocks=32768 * 64 // b,
+                            block_objects=b)
+        w.heap.set_launch(**{k: v for k, v in cfg.items() if k in S.LAUNCH_FIELDS})
+        w.heap.set_tuning(0, cfg["lookups"], 0)
+        w.populate()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(100):
+            w.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = (w.state(), w.heap.status())
+        w.release()
+        return dt, st
+
+    def same_wator(a, b):
+        return all(np.array_equal(x, y) for x, y in zip(a[0], b[0])) and a[1] == b[1] == 0
+    rec = tune.search(wator, {"block_objects": [64, 32], "lookups": [5, 3, 8], "doall_waves_per_cu": [32, 48, 64],
+                              "doall_units": [16384, 4096, 65536]}, reps=3, equal=same_wator)
+    tune.save(cache, "predator-prey 1024x1024 100 steps", rec)
+    out["predator_prey"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}
+    out["predator_prey"]["rejected"] = sum(not t["same_result"] for t in rec["trials"])
 
     # Life-like step: 200 steps, graph replay of the whole run
     def life(cfg):

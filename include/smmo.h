@@ -171,6 +171,19 @@ int smmo_heap_bytes(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_bloc
 int smmo_heap_create(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks,
                      void* dev_mem, uint64_t dev_bytes, void* stream, smmo_heap** out);
 
+/* The same with a block capacity other than the paper's: block_objects
+ * (1..64) objects per block for the smallest class, N_T = floor(block_objects
+ * * size(T_s) / size(T)) for the others (Sec. 3.2 with 64 replaced; slots
+ * from N_T to 63 of a block's allocation word stay set as padding, App. A.1).
+ * A layout parameter the autotuner searches; results of a workload do not
+ * depend on it.  block_objects = 64 is smmo_heap_bytes / smmo_heap_create.
+ * Errors as those, and SMMO_EINVAL for block_objects outside 1..64 or a class
+ * more than block_objects times the smallest. */
+int smmo_heap_bytes_ex(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks, uint32_t block_objects,
+                       uint64_t* bytes_out);
+int smmo_heap_create_ex(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks, uint32_t block_objects,
+                        void* dev_mem, uint64_t dev_bytes, void* stream, smmo_heap** out);
+
 /* Free the host handle (never the device buffer).  NULL is accepted. */
 int smmo_heap_destroy(smmo_heap* heap);
 
@@ -183,6 +196,8 @@ int smmo_class_layout(const smmo_heap* heap, uint32_t cls, smmo_layout* out);
 /* Same layout computed from the class descriptors alone, without a heap
  * (host-side only).  Errors: SMMO_EINVAL. */
 int smmo_layout_compute(const smmo_class_desc* cls, uint32_t ncls, uint32_t which, smmo_layout* out);
+int smmo_layout_compute_ex(const smmo_class_desc* cls, uint32_t ncls, uint32_t block_objects, uint32_t which,
+                           smmo_layout* out);
 
 /* Tuning: flags SMMO_TUNE_*, lookups = active-block lookup attempts before
  * the slow path (paper default 5; 1..64), force_fail_ppm for SMMO_TUNE_FORCE_FAIL.

@@ -25,15 +25,17 @@ def flatten(specs):
     return out
 
 
-def capacity(classes, t: int) -> int:
+def capacity(classes, t: int, block_objects: int = 64) -> int:
+    """N_T; with block_objects B < 64 the smallest class holds B objects per
+    block instead of 64 and the formula scales the others the same way."""
     sizes = [sum(c) for c in classes]
-    n = (64 * min(sizes)) // sizes[t]
+    n = (block_objects * min(sizes)) // sizes[t]
     if n < 1:
-        raise ValueError("class more than 64x bigger than the smallest class")
+        raise ValueError("class more than %dx bigger than the smallest class" % block_objects)
     return n
 
 
-def layout(classes, align_bytes: int = 128):
+def layout(classes, align_bytes: int = 128, block_objects: int = 64):
     """classes: list of lists of field byte sizes.
 
     Returns (block_bytes, [(capacity, [field offsets])...]).
@@ -41,7 +43,7 @@ def layout(classes, align_bytes: int = 128):
     out = []
     block = 0
     for t, fields in enumerate(classes):
-        n = capacity(classes, t)
+        n = capacity(classes, t, block_objects)
         offs, cur = [], 0
         for f in fields:
             offs.append(cur)

@@ -100,11 +100,15 @@ inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 inline unsigned grid_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
 // Layout of every class (Sec. 3.2): a class's fields are its superclass's
-// (inherited, first) followed by its own; N_T = floor(64 * size(T_s) /
-// size(T)); SOA arrays in field order, each starting on a 128-B boundary;
+// (inherited, first) followed by its own; N_T = floor(B * size(T_s) /
+// size(T)) with B = objects per block of the smallest class (the paper's 64,
+// the width of a block's allocation word; fewer leaves the upper bits as
+// padding); SOA arrays in field order, each starting on a 128-B boundary;
 // every block has the size of the largest class layout.
-int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_raw_header* hdr) {
+int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_raw_header* hdr,
+                   uint32_t block_objects = 64) {
     if (!cls || ncls == 0 || ncls > SMMO_MAX_CLASSES) return fail(SMMO_EINVAL, "ncls must be 1..%d", SMMO_MAX_CLASSES);
+    if (block_objects < 1 || block_objects > 64) return fail(SMMO_EINVAL, "block_objects must be 1..64");
     if (M == 0 || M > (1ull << 32)) return fail(SMMO_EINVAL, "num_blocks must be 1..2^32");
     std::memset(hdr, 0, sizeof *hdr);
     uint64_t size[SMMO_MAX_CLASSES];
@@ -135,8 +139,9 @@ int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_r
     }
     uint64_t block = 0;
     for (uint32_t t = 0; t < ncls; ++t) {
-        uint64_t n = 64 * smin / size[t];
-        if (n < 1) return fail(SMMO_EINVAL, "class %u is more than 64x the smallest class", t);
+        uint64_t n = block_objects * smin / size[t];
+        if (n < 1)
+            return fail(SMMO_EINVAL, "class %u is more than %ux the smallest class", t, block_objects);
         hdr->capacity[t] = n;
         uint64_t off = 0;
         for (uint32_t f = 0; f < hdr->nfields[t]; ++f) {
@@ -505,8 +510,13 @@ int launch_alloc(smmo_heap* H, uint32_t cls, uint64_t nthreads, uint32_t per, co
 extern "C" {
 
 int smmo_heap_bytes(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks, uint64_t* bytes_out) {
+    return smmo_heap_bytes_ex(cls, ncls, num_blocks, 64, bytes_out);
+}
+
+int smmo_heap_bytes_ex(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks, uint32_t block_objects,
+                       uint64_t* bytes_out) {
     smmo_raw_header h;
-    int rc = compute_layout(cls, ncls, num_blocks, &h);
+    int rc = compute_layout(cls, ncls, num_blocks, &h, block_objects);
     if (rc) return rc;
     if (!bytes_out) return fail(SMMO_EINVAL, "null bytes_out");
     *bytes_out = h.total_bytes;
@@ -515,10 +525,15 @@ int smmo_heap_bytes(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_bloc
 
 int smmo_heap_create(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks, void* dev_mem,
                      uint64_t dev_bytes, void* stream, smmo_heap** out) {
+    return smmo_heap_create_ex(cls, ncls, num_blocks, 64, dev_mem, dev_bytes, stream, out);
+}
+
+int smmo_heap_create_ex(const smmo_class_desc* cls, uint32_t ncls, uint64_t num_blocks, uint32_t block_objects,
+                        void* dev_mem, uint64_t dev_bytes, void* stream, smmo_heap** out) {
     if (!out || !dev_mem) return fail(SMMO_EINVAL, "null out or dev_mem");
     if (reinterpret_cast<uintptr_t>(dev_mem) % 256) return fail(SMMO_EINVAL, "dev_mem must be 256-B aligned");
     smmo_heap* H = new smmo_heap();
-    int rc = compute_layout(cls, ncls, num_blocks, &H->hdr);
+    int rc = compute_layout(cls, ncls, num_blocks, &H->hdr, block_objects);
     if (rc) { delete H; return rc; }
     if (dev_bytes < H->hdr.total_bytes) {
         unsigned long long need = H->hdr.total_bytes;
@@ -595,8 +610,13 @@ int smmo_class_layout(const smmo_heap* heap, uint32_t cls, smmo_layout* out) {
 }
 
 int smmo_layout_compute(const smmo_class_desc* cls, uint32_t ncls, uint32_t which, smmo_layout* out) {
+    return smmo_layout_compute_ex(cls, ncls, 64, which, out);
+}
+
+int smmo_layout_compute_ex(const smmo_class_desc* cls, uint32_t ncls, uint32_t block_objects, uint32_t which,
+                           smmo_layout* out) {
     smmo_heap tmp;
-    int rc = compute_layout(cls, ncls, 1, &tmp.hdr);
+    int rc = compute_layout(cls, ncls, 1, &tmp.hdr, block_objects);
     if (rc) return rc;
     return smmo_class_layout(&tmp, which, out);
 }

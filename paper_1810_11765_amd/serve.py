@@ -47,13 +47,13 @@ def make_requests(seed: int = 42, count: int = 256, rate: float = 50.0, lo: int 
     return out
 
 
-def arena_bytes_for(reqs) -> int:
+def arena_bytes_for(reqs, block_objects: int = 64) -> int:
     """Arena size that holds every request at once (plus batch tables: the
     persistent kernel's barrier words take ~8.5 KB per slot)."""
     tot = (1 << 22) + 9 * 1024 * len(reqs)
     for r in reqs:
         n = r.side * r.side
-        tot += S.heap_bytes(WaTor.CLASSES, wator_blocks(r.kind0)) + 16 * n + 4096
+        tot += S.heap_bytes(WaTor.CLASSES, wator_blocks(r.kind0, block_objects), block_objects) + 16 * n + 4096
     return tot
 
 
@@ -68,17 +68,18 @@ class Fleet:
     remaining)), so finding finished instances needs no device readback; the
     device's own count is checked once, when an instance leaves."""
 
-    def __init__(self, arena: S.Arena, max_instances: int = 256, lookups: int = 5):
+    def __init__(self, arena: S.Arena, max_instances: int = 256, lookups: int = 5, block_objects: int = 64):
         self.arena = arena
         self.batch = S.Batch(arena, max_instances)
         self.lookups = lookups              # active-block lookups r of every instance heap
+        self.block_objects = block_objects  # objects per block of the smallest class (layout)
         self.live = {}                      # slot -> (request, WaTor)
         self.left = {}                      # slot -> steps still to run
 
     def admit(self, req: Request, steps: int, stream=None) -> bool:
         try:
             w = WaTor(seed=req.seed, width=req.side, height=req.side, num_blocks=None, kind0=req.kind0,
-                      arena=self.arena)
+                      arena=self.arena, block_objects=self.block_objects)
         except S.SmmoError:
             return False                    # no room in the arena yet
         if self.lookups != 5:
@@ -124,13 +125,14 @@ class Fleet:
         self.batch.close()
 
 
-def run_plain(reqs, steps: int, arena: S.Arena):
+def run_plain(reqs, steps: int, arena: S.Arena, block_objects: int = 64):
     """One instance at a time, per-phase launches.  Returns (results, seconds)."""
     results = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in reqs:
-        w = WaTor(seed=r.seed, width=r.side, height=r.side, num_blocks=None, kind0=r.kind0, arena=arena)
+        w = WaTor(seed=r.seed, width=r.side, height=r.side, num_blocks=None, kind0=r.kind0, arena=arena,
+                  block_objects=block_objects)
         w.populate()
         for _ in range(steps):
             w.step()
@@ -141,12 +143,12 @@ def run_plain(reqs, steps: int, arena: S.Arena):
 
 
 def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bool = False, wg_per_cu: int = 0,
-                lookups: int = 5):
+                lookups: int = 5, block_objects: int = 64):
     """All instances admitted, then `steps` steps of the persistent kernel
     (`per_launch` steps per launch, wg_per_cu workgroups per CU, 0 = all that
     fit; `lookups` active-block lookups per allocation).  Returns (results,
     seconds of the stepping, grid workgroups)."""
-    fleet = Fleet(arena, max(len(reqs), 1), lookups=lookups)
+    fleet = Fleet(arena, max(len(reqs), 1), lookups=lookups, block_objects=block_objects)
     fleet.batch.set_grid(wg_per_cu)
     for r in reqs:
         assert fleet.admit(r, steps), "arena too small for the whole batch"
@@ -177,7 +179,7 @@ def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bo
 
 
 def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instances: int = 256,
-          wg_per_cu: int = 0, lookups: int = 5, steps_per_tick: int = 10):
+          wg_per_cu: int = 0, lookups: int = 5, steps_per_tick: int = 10, block_objects: int = 64):
     """Continuous batching over arrivals (arrival times scaled by time_scale):
     between launches, arrived requests are admitted while the arena has room;
     each launch advances every live instance by up to `steps_per_tick` steps
@@ -188,7 +190,7 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
     the launch's GPU time over its steps, one entry per live instance and
     step), wall seconds, busy seconds (GPU time of the launches), admission
     host times (ms, outside the latencies) and admission delays."""
-    fleet = Fleet(arena, max(1, min(max_instances, len(reqs))), lookups=lookups)
+    fleet = Fleet(arena, max(1, min(max_instances, len(reqs))), lookups=lookups, block_objects=block_objects)
     fleet.batch.set_grid(wg_per_cu)
     pending = deque(sorted(reqs, key=lambda r: r.arrival))
     lat, admit_delay, admit_ms, results = [], [], [], {}

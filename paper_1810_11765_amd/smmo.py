@@ -136,6 +136,9 @@ def lib():
             "smmo_heap_reset": ([P, P], i),
             "smmo_class_layout": ([P, u32, P], i),
             "smmo_layout_compute": ([P, u32, u32, P], i),
+            "smmo_heap_bytes_ex": ([P, u32, u64, u32, P], i),
+            "smmo_heap_create_ex": ([P, u32, u64, u32, P, u64, P, P], i),
+            "smmo_layout_compute_ex": ([P, u32, u32, u32, P], i),
             "smmo_set_tuning": ([P, u32, u32, u32, P], i),
             "smmo_parallel_new": ([P, u32, u64, u32, P, u64, P], i),
             "smmo_parallel_alloc": ([P, u32, u64, u32, u32, P, u64, P], i),
@@ -206,18 +209,18 @@ def _descs(classes):
     return descs, arrs
 
 
-def layout_of(classes, cls: int) -> Layout:
+def layout_of(classes, cls: int, block_objects: int = 64) -> Layout:
     """Layout of class `cls` computed by the library without a heap."""
     descs, _keep = _descs(classes)
     out = Layout()
-    check(lib().smmo_layout_compute(descs, len(classes), cls, C.byref(out)))
+    check(lib().smmo_layout_compute_ex(descs, len(classes), block_objects, cls, C.byref(out)))
     return out
 
 
-def heap_bytes(classes, num_blocks: int) -> int:
+def heap_bytes(classes, num_blocks: int, block_objects: int = 64) -> int:
     descs, _keep = _descs(classes)
     out = C.c_uint64()
-    check(lib().smmo_heap_bytes(descs, len(classes), num_blocks, C.byref(out)))
+    check(lib().smmo_heap_bytes_ex(descs, len(classes), num_blocks, block_objects, C.byref(out)))
     return out.value
 
 
@@ -239,12 +242,14 @@ class Heap:
     device tensor owned by this object.  `classes` holds every class's full
     field list afterwards, inherited fields first."""
 
-    def __init__(self, classes, num_blocks: int, device="cuda", stream=None, dev_ptr: int | None = None):
+    def __init__(self, classes, num_blocks: int, device="cuda", stream=None, dev_ptr: int | None = None,
+                 block_objects: int = 64):
         import torch
         self.specs = list(classes)
         self.classes = full_fields(self.specs)
         self.num_blocks = num_blocks
-        nbytes = heap_bytes(self.specs, num_blocks)
+        self.block_objects = block_objects
+        nbytes = heap_bytes(self.specs, num_blocks, block_objects)
         if dev_ptr is None:
             # 4 KiB slack so the buffer can be aligned to 256 bytes
             self.buf = torch.empty(nbytes + 4096, dtype=torch.uint8, device=device)
@@ -256,8 +261,8 @@ class Heap:
         self.nbytes = nbytes
         descs, _keep = _descs(self.specs)
         h = C.c_void_p()
-        check(lib().smmo_heap_create(descs, len(self.classes), num_blocks, C.c_void_p(self.base), nbytes,
-                                     _stream(stream), C.byref(h)))
+        check(lib().smmo_heap_create_ex(descs, len(self.classes), num_blocks, block_objects, C.c_void_p(self.base),
+                                        nbytes, _stream(stream), C.byref(h)))
         self.h = h
         self.layouts = [self.layout(t) for t in range(len(self.classes))]
 

@@ -162,14 +162,16 @@ class LifeGrid:
         return alive, ages
 
 
-def wator_blocks(kind0: np.ndarray) -> int:
+def wator_blocks(kind0: np.ndarray, block_objects: int = 64) -> int:
     """Heap blocks for a predator-prey instance: room for every cell holding
-    an object of the largest class (capacity 42) plus 50% for fragmentation,
-    plus 64.  The oracle shows the population peaking at up to ~3.15x its
-    initial size under these rules, so "2x the initial object count" runs out
-    of blocks; this bound holds at any population."""
+    an object of the largest class (capacity 42 with 64 objects per block of
+    the smallest class, floor(block_objects * 8 / 12) in general) plus 50% for
+    fragmentation, plus 64.  The oracle shows the population peaking at up to
+    ~3.15x its initial size under these rules, so "2x the initial object
+    count" runs out of blocks; this bound holds at any population."""
     n = int(kind0.size)
-    return (3 * n + 83) // 84 + 64
+    cap = (block_objects * 8) // 12
+    return (3 * n + 2 * cap - 1) // (2 * cap) + 64
 
 
 class WaTor:
@@ -181,25 +183,25 @@ class WaTor:
 
     def __init__(self, seed=42, width=1024, height=1024, num_blocks=32768, fish=0.20, shark=0.05,
                  fish_breed=3, shark_breed=8, eat_gain=4, shark_e0=4, device="cuda",
-                 kind0: np.ndarray | None = None, arena: "S.Arena | None" = None):
+                 kind0: np.ndarray | None = None, arena: "S.Arena | None" = None, block_objects: int = 64):
         self.seed, self.W, self.H = seed, width, height
         self.params = dict(fish_breed=fish_breed, shark_breed=shark_breed, eat_gain=eat_gain, shark_e0=shark_e0)
         n = width * height
         self.kind0 = inputs.wator_initial(seed, width, height, fish, shark) if kind0 is None else kind0
         self.arena, self.region = arena, None
         if num_blocks is None:
-            num_blocks = wator_blocks(self.kind0)
+            num_blocks = wator_blocks(self.kind0, block_objects)
         if arena is None:
-            self.heap = S.Heap(self.CLASSES, num_blocks, device=device)
+            self.heap = S.Heap(self.CLASSES, num_blocks, device=device, block_objects=block_objects)
             self.occ = torch.zeros(n, dtype=torch.int64, device=device)
             self.claim = torch.full((n,), INT32_MAX, dtype=torch.int32, device=device)
             self.want = torch.zeros(n, dtype=torch.int32, device=device)
         else:
             # one arena range: heap, then the three grids
-            hb = (S.heap_bytes(self.CLASSES, num_blocks) + 255) // 256 * 256
+            hb = (S.heap_bytes(self.CLASSES, num_blocks, block_objects) + 255) // 256 * 256
             gb = (8 * n + 255) // 256 * 256 + 2 * ((4 * n + 255) // 256 * 256)
             self.region = arena.alloc(hb + gb)
-            self.heap = S.Heap(self.CLASSES, num_blocks, dev_ptr=self.region)
+            self.heap = S.Heap(self.CLASSES, num_blocks, dev_ptr=self.region, block_objects=block_objects)
             p = self.region + hb
             self.occ = arena.view(p, n, torch.int64); p += (8 * n + 255) // 256 * 256
             self.claim = arena.view(p, n, torch.int32); p += (4 * n + 255) // 256 * 256

@@ -168,3 +168,17 @@ def test_wator_ragged_parity(Wd, Hd, blocks, seed):
     for s in range(120):
         w.step()
     _wator_check(w, 120, core.c3_run(w.kind0, Wd, Hd, seed, 120))
+
+
+@pytest.mark.parametrize("bo,blocks", [(32, 65536), (16, 131072)])
+def test_wator_parity_with_fewer_objects_per_block(bo, blocks):
+    """The layout knob: bo objects per block of the smallest class (fish
+    blocks hold bo fish, shark blocks bo * 8 // 12), at the same heap bytes
+    as the 64-object default.  1024 x 1024, seed 3, 60 steps."""
+    say("wator block objects", bo, blocks)
+    w = W().WaTor(seed=3, num_blocks=blocks, block_objects=bo)
+    assert w.heap.layout(0).capacity == bo and w.heap.layout(1).capacity == bo * 8 // 12
+    w.populate()
+    for s in range(60):
+        w.step()
+    _wator_check(w, 60, core.c3_run(w.kind0, 1024, 1024, 3, 60))

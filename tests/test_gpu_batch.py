@@ -77,10 +77,25 @@ def test_batched_with_the_tuned_shape_matches_oracle():
     say("batched tuned", shape)
     sv = SV()
     reqs = sv.make_requests(seed=17, count=24, lo=16, hi=160)
-    arena = S().Arena(sv.arena_bytes_for(reqs))
+    bo = shape.get("block_objects", 64)
+    arena = S().Arena(sv.arena_bytes_for(reqs, bo))
     results, dt, grid = sv.run_batched(reqs, 50, arena, per_launch=shape["steps_per_launch"], graph=True,
-                                       wg_per_cu=shape["wg_per_cu"], lookups=shape.get("lookups", 5))
+                                       wg_per_cu=shape["wg_per_cu"], lookups=shape.get("lookups", 5),
+                                       block_objects=bo)
     _check(results, reqs, 50)
+
+
+def test_batched_and_served_with_32_object_blocks_match_oracle():
+    """Every instance's heap laid out with 32 objects per fish block (the
+    autotuner's other layout candidate), batched and served."""
+    say("batched 32-object blocks")
+    sv = SV()
+    reqs = sv.make_requests(seed=19, count=10, lo=16, hi=140)
+    arena = S().Arena(sv.arena_bytes_for(reqs, 32))
+    results, dt, grid = sv.run_batched(reqs, 40, arena, per_launch=4, graph=True, block_objects=32)
+    _check(results, reqs, 40)
+    out = sv.serve(reqs, 40, arena, time_scale=1.0, block_objects=32)
+    _check(out["results"], reqs, 40)
 
 
 def test_plain_one_by_one_matches_oracle():
@@ -157,10 +172,11 @@ def test_config_5_batched_and_served_against_oracle_goldens():
     assert sorted(golden) == [r.rid for r in reqs]
     for r in reqs:
         assert golden[r.rid][:2] == (r.side, r.seed)
-    shape = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5}
+    shape = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5, "block_objects": 64}
     path = os.path.join(os.path.dirname(sv.__file__), "tuned_launch.json")
     shape.update(tune.load(path, "predator-prey batched 256 instances 200 steps") or {})
-    arena = S().Arena(sv.arena_bytes_for(reqs))
+    bo = shape["block_objects"]
+    arena = S().Arena(sv.arena_bytes_for(reqs, bo))
 
     def check(results, what):
         bad = []
@@ -173,10 +189,11 @@ def test_config_5_batched_and_served_against_oracle_goldens():
 
     say("config 5 batched", shape)
     results, dt, _ = sv.run_batched(reqs, 200, arena, per_launch=shape["steps_per_launch"], graph=True,
-                                    wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"])
+                                    wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"], block_objects=bo)
     check(results, "batched")
     say("config 5 served")
-    out = sv.serve(reqs, 200, arena, time_scale=1.0, wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"])
+    out = sv.serve(reqs, 200, arena, time_scale=1.0, wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"],
+                   steps_per_tick=shape["steps_per_launch"], block_objects=bo)
     check(out["results"], "served")
 
 

@@ -53,6 +53,27 @@ def test_layout_matches_capacity_formula(classes):
         assert list(lay.field_bytes[: len(offs)]) == classes[t]
 
 
+@pytest.mark.parametrize("block_objects", [1, 21, 32, 63])
+@pytest.mark.parametrize("classes", WORKLOAD_CLASSES[:4])
+def test_layout_with_fewer_objects_per_block_matches_the_formula(classes, block_objects):
+    try:
+        block, per = layout_ref.layout(classes, block_objects=block_objects)
+    except ValueError:                                   # a class too big for this capacity:
+        with pytest.raises(S.SmmoError):                 # the library refuses it too
+            S.layout_of(classes, 0, block_objects)
+        return
+    for t, (n, offs) in enumerate(per):
+        lay = S.layout_of(classes, t, block_objects)
+        assert lay.capacity == n and lay.block_bytes == block
+        assert list(lay.field_offset[: len(offs)]) == offs
+
+
+def test_block_objects_out_of_range_is_rejected():
+    for bad in (0, 65):
+        with pytest.raises(S.SmmoError):
+            S.heap_bytes([[4]], 16, bad)
+
+
 def test_layout_with_subclasses_by_hand():
     """Base {i32, i32}; Sub: Base + {f64}; Leaf: Sub + nothing; Tiny {i8, i8}.
     Sizes 8, 16, 16, 2: capacities 64*2 // size = 16, 8, 8, 64; SOA arrays of

@@ -27,3 +27,15 @@ def test_class_more_than_64x_bigger_is_rejected():
     with pytest.raises(ValueError):
         L.capacity([[1], [8] * 9], 1)          # 72 B vs 1 B
     assert L.capacity([[1], [8] * 8], 1) == 1   # exactly 64 x
+
+
+def test_block_capacity_parameter_by_hand():
+    """With 32 objects per block for the smallest class (the autotuner's
+    other layout): Wa-Tor Fish 8 B -> 32 (arrays 128 B), Shark 12 B ->
+    floor(256/12) = 21 (arrays 84 -> 128 B); block = 3 x 128 = 384 B.  With
+    one object per block every class of size <= the smallest holds 1."""
+    assert L.layout([[4, 4], [4, 4, 4]], block_objects=32) == (384, [(32, [0, 128]), (21, [0, 128, 256])])
+    assert L.layout([[4, 4, 1], [4, 4]], block_objects=32) == (384, [(28, [0, 128, 256]), (32, [0, 128])])
+    assert L.capacity([[4]], 0, block_objects=1) == 1
+    with pytest.raises(ValueError):
+        L.capacity([[1], [8] * 5], 1, block_objects=32)     # 40 B vs 1 B > 32x
