@@ -176,17 +176,6 @@ def roofline_for(per_ms):
                   "kernel": kernel, "ms_per_launch": round(ms, 5), "bytes_per_launch": int(bytes_per[name])}
 
 
-def kernel_source_hash() -> str:
-    """Hash of the HIP sources; counter figures taken on other sources are stale."""
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1810_11765_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
-    return h.hexdigest()
-
-
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE and
     WRITE_SIZE runs recorded in paper_1810_11765_amd/hbm_traffic.json (each counter scaled by
@@ -196,6 +185,7 @@ def measured_traffic(kernel: str):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    from paper_1810_11765_amd.counters import kernel_source_hash
     if rec.get("source_sha256") != kernel_source_hash():
         return None
     k = rec.get("kernels", {}).get(kernel)
