@@ -40,9 +40,19 @@ def kernel_source_hash() -> str:
 
 
 def short_name(kernel: str, grid: int) -> str:
-    """``smmo::k_doall<smmo::MLifeCommit, false>`` -> ``k_doall<MLifeCommit>``;
-    the streaming sweep at the bench's 2^21-block shape gets ``@2^21``."""
+    """``smmo::k_doall<smmo::MLifeCommit, false>`` or ``void
+    k_doall<MLifeCommit>(DevHeap, ...)`` -> ``k_doall<MLifeCommit>`` (the
+    profiler prints either form); the streaming sweep at the bench's
+    2^21-block shape gets ``@2^21``."""
     k = kernel.replace("smmo::", "")
+    if k.startswith("void "):
+        k = k[5:]
+    depth = 0
+    for i, c in enumerate(k):               # cut the parameter list at template depth 0
+        depth += (c == "<") - (c == ">")
+        if c == "(" and depth == 0 and i > 0:
+            k = k[:i]
+            break
     k = re.sub(r", (true|false)>", ">", k)
     if k.startswith("k_doall_axpy<") and grid == SWEEP_GRID:
         k += "@2^21"

@@ -188,13 +188,14 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
 
     Returns dict with results per request, per instance-step latencies (ms:
     the launch's GPU time over its steps, one entry per live instance and
-    step), wall seconds, busy seconds (GPU time of the launches), admission
-    host times (ms, outside the latencies) and admission delays."""
+    step), wall seconds, busy seconds (GPU time of the launches), the mean
+    number of live instances per step run, admission host times (ms, outside
+    the latencies) and admission delays."""
     fleet = Fleet(arena, max(1, min(max_instances, len(reqs))), lookups=lookups, block_objects=block_objects)
     fleet.batch.set_grid(wg_per_cu)
     pending = deque(sorted(reqs, key=lambda r: r.arrival))
     lat, admit_delay, admit_ms, results = [], [], [], {}
-    busy = 0.0
+    busy, steps_run = 0.0, 0
     t0 = time.perf_counter()
     while pending or fleet.live:
         now = time.perf_counter() - t0
@@ -216,6 +217,7 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
             b.synchronize()
             ms = a.elapsed_time(b)
             busy += ms * 1e-3
+            steps_run += k
             lat.extend([ms / k] * (len(fleet.live) * k))
             for req, st, status in fleet.harvest():
                 results[req.rid] = (st, status)
@@ -224,4 +226,5 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
     wall = time.perf_counter() - t0
     fleet.close()
     return {"results": results, "latency_ms": np.array(lat), "wall_s": wall, "busy_s": busy,
+            "mean_live": len(lat) / max(1, steps_run),
             "admit_ms": np.array(admit_ms), "admit_delay_s": np.array(admit_delay)}

@@ -20,7 +20,7 @@ def _csv(path, counter, rows):
 
 
 def test_scaled_bytes_per_launch(tmp_path):
-    commit = "smmo::k_doall<smmo::MLifeCommit, false>"
+    commit = "void k_doall<MLifeCommit>(DevHeap, unsigned int, unsigned long, MLifeCommit::Args)"
     sweep = "smmo::k_doall_axpy<4>"
     # the 1 GiB copy reads half its bytes in the fetch counter's units: factor 2
     _csv(tmp_path / "f.csv", "FETCH_SIZE", [(counters.CALIB_KERNEL, 131072, 524288.0),
@@ -38,6 +38,8 @@ def test_scaled_bytes_per_launch(tmp_path):
     assert k["k_doall_axpy<4>@2^21"]["bytes_per_launch"] == (2 * 1000 + 500) * 1024
     assert k["k_doall_axpy<4>"]["bytes_per_launch"] == (2 * 10 + 5) * 1024
     assert not any(n.startswith("__amd") for n in k)
+    assert counters.short_name("smmo::k_doall<smmo::MLifeCommit, false>", 786432) == "k_doall<MLifeCommit>"
+    assert counters.short_name("k_destroy(DevHeap, unsigned long const*)", 1) == "k_destroy"
     assert rec["source_sha256"] == counters.kernel_source_hash()
     counters.main(["x", str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "o.json")])
     assert json.load(open(tmp_path / "o.json"))["kernels"] == k
