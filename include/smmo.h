@@ -595,8 +595,6 @@ int smmo_get_launch(const smmo_heap* heap, smmo_launch* out);
 int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word, uint64_t nthreads,
                       uint32_t rounds, void* stream);
 
-/* Handle layout: bits 56-63 class id + 1, bits 6-49 block, bits 0-5 slot;
- * 0 is the null handle.  Host-side helpers. */
 /* Self-check of the arithmetic the n-body force kernel uses on its fast
  * path (device_do, Sec. 2.1: correctly rounded sqrt and division where
  * operands lie in ranges that need no scaling).  Adds to counts_dev[0] (a
@@ -607,6 +605,27 @@ int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word,
  * the tests run it over the whole range [2^-40, 2^40). Asynchronous. */
 int smmo_check_force_arith(uint32_t lo_bits, uint32_t hi_bits, uint64_t pairs, uint64_t seed, uint64_t* counts_dev,
                            void* stream);
+
+/* Message-passing check of the order the allocator relies on when a block is
+ * re-initialized (Alg. 8, App. A.3): a reservation that sees a block's new
+ * allocation word must read the block's new type.  Runs the allocator's own
+ * block initialization and reservation code on a scratch block table:
+ * writer waves re-initialize each of `blocks` blocks `rounds` times (round
+ * k: type k, then the word k << 32), reader waves (on every XCD, the writers
+ * on others) OR a bit into random blocks' words and then read their types;
+ * a type older than the round the OR returned is a violation.  Every wave
+ * runs a bounded number of iterations and waits for no other wave; readers
+ * stop soon after the first violation.
+ * dev_buf: device buffer of at least 20 * blocks bytes rounded up to a
+ * multiple of 8, 8-byte aligned (overwritten).  counts_dev: device uint64[4], cleared first, then
+ * [0] samples, [1] samples that saw a re-initialized word, [2] violations
+ * (must be 0), [3] the first violation as block << 32 | type read.
+ * blocks >= 1; 1 <= rounds < 2^31.  SMMO_EINVAL otherwise.  Asynchronous. */
+int smmo_check_publish_order(void* dev_buf, uint64_t buf_bytes, uint32_t blocks, uint32_t rounds, uint64_t seed,
+                             uint64_t* counts_dev, void* stream);
+
+/* Handle layout: bits 56-63 class id + 1, bits 6-49 block, bits 0-5 slot;
+ * 0 is the null handle.  Host-side helpers. */
 
 uint64_t smmo_ref_make(uint32_t cls, uint64_t block, uint32_t slot);
 uint32_t smmo_ref_class(uint64_t ref);

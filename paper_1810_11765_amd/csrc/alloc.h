@@ -56,6 +56,18 @@ __device__ inline void initialize_block(const DevHeap& h, uint32_t cls, uint64_t
     }
 }
 
+// The reader's half of that order: an OR on a block's allocation word, after
+// which (the OR has returned before the next load is issued: its result is
+// broadcast first) block_type reads the type at the device coherence point,
+// so it is at least as new as the initialization that wrote the word the OR
+// saw.  Reservations and invalidations both use this pair.
+__device__ inline uint64_t reserve_or(const DevHeap& h, uint64_t bid, uint64_t mask) {
+    const uint64_t before = w_or(&h.alloc[bid], mask);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return before;
+}
+__device__ inline uint32_t block_type(const DevHeap& h, uint64_t bid) { return w_load32(&h.type[bid]); }
+
 // invalidate(bid) (Alg. 9, iterative).  True if this call took the block
 // from "empty" to "invalidated"; the caller then frees it.
 // The OR is relaxed: every word it races with is an agent-scope atomic, and
@@ -66,9 +78,9 @@ __device__ inline void initialize_block(const DevHeap& h, uint32_t cls, uint64_t
 __device__ inline bool invalidate_block(const DevHeap& h, uint64_t bid) {
     bid = uni64(bid);
     for (uint32_t tries = 0; tries < kSpinLimit; ++tries) {
-        const uint64_t before = w_or(&h.alloc[bid], kOnes);
+        const uint64_t before = reserve_or(h, bid, kOnes);
         if (before == kOnes) return false;          // nothing invalidated
-        const uint32_t t = w_load32(&h.type[bid]);
+        const uint32_t t = block_type(h, bid);
         if (t >= h.ncls) { w_set_status(h, SMMO_STATUS_CORRUPT); return false; }
         const uint64_t pad = h.cls_pad[t];
         if (before == pad) return true;             // every slot was free
@@ -185,12 +197,11 @@ __device__ __forceinline__ uint64_t alloc_piece(const DevHeap& h, uint32_t cls, 
         // coherence point, where the type already is.  An acquire on the OR
         // would also invalidate this CU's caches on every reservation, which
         // more than doubled the allocating do-alls' time on MI355X.
-        const uint64_t before = w_or(&h.alloc[bid], mask);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const uint64_t before = reserve_or(h, bid, mask);
         w_count(h, SMMO_CNT_RESERVE_ATOMIC);
         const uint64_t got = mask & ~before;
         if (!got) { w_count(h, SMMO_CNT_RESERVE_FAIL); continue; }
-        const uint32_t t = w_load32(&h.type[bid]);
+        const uint32_t t = block_type(h, bid);
         if (t >= h.ncls) { w_set_status(h, SMMO_STATUS_CORRUPT); continue; }
         if ((before | got) == kOnes) bm_clear(h, bm_active(h, t), bid);   // this call filled it
         if (t != cls) {                                   // block changed type: roll back
@@ -251,6 +262,47 @@ __device__ inline void wave_destroy_self(const DevHeap& h, uint32_t cls, uint64_
     if (!mask) return;
     dealloc_mask(h, cls, bid, mask);
     w_count(h, SMMO_CNT_FREE_OBJ, popc64(mask));
+}
+
+// Bounded message-passing check of initialize_block against reserve_or /
+// block_type on a scratch table (smmo_check_publish_order).  Workgroups
+// alternate roles, so writers and readers share every XCD (a workgroup runs
+// on XCD blockIdx mod 8) and a reader's random blocks are mostly written on
+// other XCDs.  out: [0] samples, [1] re-initialized words seen, [2]
+// violations, [3] first violation (block << 32 | type).
+__global__ __launch_bounds__(256) void k_check_publish(DevHeap h, uint32_t blocks, uint32_t rounds, uint64_t seed,
+                                                        unsigned long long* out) {
+    const uint32_t rank = (blockIdx.x >> 1) * (blockDim.x >> 6) + (threadIdx.x >> 6);   // wave within its role
+    const uint32_t nrole = (gridDim.x >> 1) * (blockDim.x >> 6);
+    if ((blockIdx.x & 1) == 0) {
+        for (uint32_t k = 1; k <= rounds; ++k)
+            for (uint64_t b = rank; b < blocks; b += nrole) initialize_block(h, k, b, (uint64_t)k << 32);
+        return;
+    }
+    uint64_t s = uni64(splitmix64(seed ^ ((uint64_t)rank << 20)));
+    unsigned long long samples = 0, fresh = 0;
+    const uint64_t n = 2ull * rounds * ((blocks + nrole - 1) / nrole);
+    for (uint64_t j = 0; j < n; ++j) {
+        if ((j & 63) == 0 && w_load(reinterpret_cast<const uint64_t*>(&out[2])) != 0) break;
+        s = splitmix64(s);
+        const uint64_t b = s % blocks;
+        const uint64_t before = reserve_or(h, b, 1ull << (j & 31));
+        const uint32_t t = block_type(h, b);
+        const uint32_t k = (uint32_t)(before >> 32);
+        ++samples;
+        fresh += k != 0;
+        if (t < k) {
+            if (is_first_lane()) {
+                atomicAdd(&out[2], 1ull);
+                atomicCAS(&out[3], 0ull, (unsigned long long)((b << 32) | t));
+            }
+            break;
+        }
+    }
+    if (is_first_lane()) {
+        atomicAdd(&out[0], samples);
+        atomicAdd(&out[1], fresh);
+    }
 }
 
 }  // namespace smmo

@@ -43,7 +43,10 @@ constexpr uint64_t kUnitMask = (1ull << kBatchUnit) - 1;
 // polls and increments of one line queue behind each other at the memory
 // side); here at most kBarGroup increments meet on a group line, and the
 // polled word changes once per barrier.  On gfx950 an agent-scope acquire
-// invalidates the XCD's L2, so only group leaders take one on arrival.
+// invalidates the XCD's L2, so only group leaders take one on arrival.  An
+// instance of a single group (most instances of a large batch) polls its
+// group counter directly: the hop through the opening word would add an
+// acquire and a release (an L2 invalidation and write-back) to every barrier.
 // Layout of an instance's region (uint32 words, zeroed before each launch):
 // [0] top counter, [32] number of the last barrier opened, [64 + 32 g] the
 // counter of group g (each on its own 128-B line).
@@ -56,24 +59,30 @@ __device__ inline void instance_barrier(uint32_t* bar, uint32_t number, uint32_t
         const uint32_t g = rank / kBarGroup;
         const uint32_t gsize = nwg - g * kBarGroup < kBarGroup ? nwg - g * kBarGroup : kBarGroup;
         const uint32_t ngroups = (nwg + kBarGroup - 1) / kBarGroup;
-        const uint32_t old = __hip_atomic_fetch_add(&bar[64 + 32 * g], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1 == number * gsize) {                        // last of its group
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            // an instance of one group opens the barrier at once
-            const uint32_t t =
-                ngroups == 1 ? number - 1 : __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            if (t + 1 == number * ngroups) {                    // last group: open the barrier
-                if (ngroups > 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                __hip_atomic_store(&bar[32], number, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t* gcnt = &bar[64 + 32 * g];
+        const uint32_t old = __hip_atomic_fetch_add(gcnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // one group: the group counter itself opens the barrier at nwg * number
+        const uint32_t* poll = gcnt;
+        uint32_t target = number * gsize;
+        if (ngroups > 1) {
+            poll = &bar[32];
+            target = number;
+            if (old + 1 == number * gsize) {                    // last of its group
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const uint32_t t = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (t + 1 == number * ngroups) {                // last group: open the barrier
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    __hip_atomic_store(&bar[32], number, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
         }
         uint32_t spins = 0;
-        while (__hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < number) {
+        while (__hip_atomic_load(poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (++spins > kBarrierSpin) {
                 __hip_atomic_fetch_or(status, SMMO_STATUS_RETRY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
-            if (spins < 8) __builtin_amdgcn_s_sleep(1);        // back off after the first polls
+            if (ngroups == 1 || spins < 8) __builtin_amdgcn_s_sleep(1);    // back off after the first polls
             else __builtin_amdgcn_s_sleep(4);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

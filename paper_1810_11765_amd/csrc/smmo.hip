@@ -890,6 +890,32 @@ int smmo_check_force_arith(uint32_t lo_bits, uint32_t hi_bits, uint64_t pairs, u
     return SMMO_OK;
 }
 
+int smmo_check_publish_order(void* dev_buf, uint64_t buf_bytes, uint32_t blocks, uint32_t rounds, uint64_t seed,
+                             uint64_t* counts_dev, void* stream) {
+    if (!dev_buf || !counts_dev) return fail(SMMO_EINVAL, "check_publish_order: null argument");
+    if (blocks == 0 || rounds == 0 || rounds >= (1u << 31))
+        return fail(SMMO_EINVAL, "check_publish_order: blocks %u, rounds %u out of range", blocks, rounds);
+    const uint64_t words = (20ull * blocks + 7) / 8;
+    if (reinterpret_cast<uintptr_t>(dev_buf) % 8 || buf_bytes < 8 * words)
+        return fail(SMMO_EINVAL, "check_publish_order: buffer of %llu bytes (8-aligned, %llu needed)",
+                    (unsigned long long)buf_bytes, (unsigned long long)(8 * words));
+    hipStream_t s = S(stream);
+    // table: alloc words, iteration words, then types
+    DevHeap h;
+    std::memset(&h, 0, sizeof h);
+    h.alloc = reinterpret_cast<uint64_t*>(dev_buf);
+    h.iter = h.alloc + blocks;
+    h.type = reinterpret_cast<uint32_t*>(h.iter + blocks);
+    h.M = blocks;
+    k_fill_u64<<<grid_for(words, 256), 256, 0, s>>>(reinterpret_cast<unsigned long long*>(dev_buf), words, 0);
+    LAUNCH_CHECK("k_fill_u64");
+    k_fill_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long*>(counts_dev), 4, 0);
+    LAUNCH_CHECK("k_fill_u64");
+    k_check_publish<<<2048, 256, 0, s>>>(h, blocks, rounds, seed, reinterpret_cast<unsigned long long*>(counts_dev));
+    LAUNCH_CHECK("k_check_publish");
+    return SMMO_OK;
+}
+
 int smmo_occupancy(smmo_heap* heap, uint64_t* used, uint64_t* slots, uint64_t* blocks, void* stream) {
     TimingScope timing(heap, false);
     if (!heap) return fail(SMMO_EINVAL, "null heap");

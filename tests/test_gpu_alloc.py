@@ -153,6 +153,36 @@ def test_capacity_one_class_churn_matches_oracle(seed):
         assert s["blocks"] == [0, nthreads * per]
 
 
+@pytest.mark.parametrize("blocks,rounds", [(1, 2000), (96, 2000), (4099, 200), (65536, 40)])
+def test_publication_order_message_passing(blocks, rounds):
+    """smmo_check_publish_order: the allocator's block initialization
+    (type, then the word once the type store has completed) against its
+    reservation (OR on the word, then the type): writer waves re-initialize
+    blocks round after round while reader waves on every XCD OR into random
+    blocks and read the type; no reader may see a word newer than the type.
+    Bounded: no wave waits for another."""
+    import ctypes as C
+    say("publish order", blocks, rounds)
+    L = S().lib()
+    L.smmo_check_publish_order.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p,
+                                           C.c_void_p]
+    L.smmo_check_publish_order.restype = C.c_int
+    nbytes = (20 * blocks + 7) // 8 * 8
+    buf = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda")
+    out = torch.full((4,), 7, dtype=torch.int64, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    S().check(L.smmo_check_publish_order(buf.data_ptr(), nbytes, blocks, rounds, 5, out.data_ptr(), stream))
+    samples, fresh, bad, first = out.cpu().tolist()
+    assert bad == 0, f"{bad} readers saw a newer word than type (first: block {first >> 32}, type {first & 0xFFFFFFFF})"
+    assert samples > 0 and fresh > samples // 2, (samples, fresh)
+    # the writers ran to completion: every block ends at the last round
+    words = buf[:blocks].cpu().numpy().view(np.uint64) >> np.uint64(32)
+    types = buf.cpu().numpy().view(np.uint32)[4 * blocks:5 * blocks]
+    assert (words == rounds).all() and (types == rounds).all()
+    with pytest.raises(S().SmmoError):
+        S().check(L.smmo_check_publish_order(buf.data_ptr(), nbytes - 8, blocks + 1, rounds, 5, out.data_ptr(), stream))
+
+
 def test_every_live_object_visited_exactly_once():
     say("visit")
     smmo = S()
