@@ -29,6 +29,8 @@ sys.path.insert(0, ROOT)
 METRIC = "alloc+destroy Mobj/s; parallel_do GB/s (% HBM peak); app steps/s plain vs batched"
 TUNED_LAUNCH = os.path.join(ROOT, "paper_1810_11765_amd", "tuned_launch.json")
 HBM_PEAK_GBS = 8000.0
+CLOCK_HZ = 2.4e9                  # MI355X peak engine clock
+SIMDS = 256 * 4                   # compute units x SIMDs per unit
 HOLD_CYCLES = 1 << 28           # spin-kernel length that holds the stream while launches are queued
 
 
@@ -333,10 +335,37 @@ def nbody_sub(torch, workloads, steps=2):
     f = sum(tm.ms("force")) / steps
     inter = n * (n - 1)
     tf = 14.0 * inter / (f * 1e-3) / 1e12
+    status = nb.heap.status()
+    del nb
+    # issue cost of the force kernel's instruction kinds (smmo_valu_probe at 8
+    # waves per SIMD): cycles one SIMD spends per wave-instruction, and the
+    # force kernel's time if every SIMD issued its instructions back to back
+    # (mix per interaction from the SQ_INSTS_VALU counter run: 30.1 VALU
+    # lane-instructions, one square root and one reciprocal among them)
+    import ctypes as C
+    L = S.lib()
+    L.smmo_valu_probe.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p]
+    L.smmo_valu_probe.restype = C.c_int
+    wgs, iters = 2048, 20000
+    out = torch.empty(wgs * 256, dtype=torch.float32, device="cuda")
+    cyc = {}
+    for kind, name in ((1, "fma"), (2, "sqrt"), (3, "rcp")):
+        t = Timer(torch)
+        for _ in range(3):
+            t.run(name, lambda: S.check(L.smmo_valu_probe(out.data_ptr(), kind, wgs, iters,
+                                                          C.c_void_p(torch.cuda.current_stream().cuda_stream))))
+        torch.cuda.synchronize()
+        ms = min(t.ms(name))
+        cyc[name] = ms * 1e-3 * CLOCK_HZ * SIMDS / (wgs * 4 * iters * 8)
+    per_inter = (30.1 - 2) * cyc["fma"] + cyc["sqrt"] + cyc["rcp"]      # SIMD cycles per wave-interaction
+    bound_ms = inter / 64 * per_inter / (SIMDS * CLOCK_HZ) * 1e3
     return {"bodies_live": n, "ms_per_step": round((sum(tm.ms("merge")) + sum(tm.ms("force")) + sum(tm.ms("move"))) / steps, 3),
             "force_ms": round(f, 3), "merge_ms": round(sum(tm.ms("merge")) / steps, 3),
             "interactions_per_s": round(inter / (f * 1e-3), 1), "fp32_tflops_at_14_per_interaction": round(tf, 2),
-            "fp32_vector_peak_frac": round(tf / 157.3, 4), "status": nb.heap.status()}
+            "fp32_vector_peak_frac": round(tf / 157.3, 4),
+            "valu_cycles_per_wave_instruction": {k: round(v, 3) for k, v in cyc.items()},
+            "force_issue_bound_ms": round(bound_ms, 2), "force_frac_of_issue_bound": round(bound_ms / f, 3),
+            "status": status}
 
 
 def sweep_sub(torch, nblocks):

@@ -595,6 +595,15 @@ int smmo_get_launch(const smmo_heap* heap, smmo_launch* out);
 int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word, uint64_t nthreads,
                       uint32_t rounds, void* stream);
 
+/* VALU issue-cost reference for the n-body force kernel (not part of the
+ * method): `workgroups` workgroups of 256 threads each run eight independent
+ * chains of `iters` instructions of one kind per lane (kind 0: FP32 add,
+ * 1: FP32 fma, 2: hardware square root, 3: hardware reciprocal) and store one
+ * float per thread into out (a device array of workgroups * 256 floats).
+ * Time it with events: wave-instructions = workgroups * 4 * iters * 8.
+ * kind > 3, workgroups 0 or a null out: SMMO_EINVAL.  Asynchronous. */
+int smmo_valu_probe(float* out, uint32_t kind, uint32_t workgroups, uint32_t iters, void* stream);
+
 /* Self-check of the arithmetic the n-body force kernel uses on its fast
  * path (device_do, Sec. 2.1: correctly rounded sqrt and division where
  * operands lie in ranges that need no scaling).  Adds to counts_dev[0] (a

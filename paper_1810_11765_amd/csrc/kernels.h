@@ -382,6 +382,23 @@ __global__ __launch_bounds__(kBlockThreads) void k_atomic_probe(unsigned long lo
     if (lane_id() == 0 && acc == 0x5bd1e995ull) words[0] = acc;   // practically never taken
 }
 
+// VALU issue-cost reference (not part of the method): eight independent
+// chains of one instruction kind per lane, `iters` times; kind 0 FP32 add,
+// 1 FP32 fma, 2 hardware square root, 3 hardware reciprocal; the constant
+// operand c comes in a scalar register.  The chains' ends are folded into one
+// store so that nothing is optimized away.
+__global__ __launch_bounds__(256) void k_valu_probe(float* out, uint32_t kind, uint32_t iters, float c) {
+    float v[8];
+    for (int k = 0; k < 8; ++k) v[k] = 1.0f + (float)(threadIdx.x + k) * 0x1p-12f;
+    switch (kind) {
+        case 0: for (uint32_t i = 0; i < iters; ++i) for (int k = 0; k < 8; ++k) v[k] = v[k] + c; break;
+        case 1: for (uint32_t i = 0; i < iters; ++i) for (int k = 0; k < 8; ++k) v[k] = __builtin_fmaf(v[k], c, c); break;
+        case 2: for (uint32_t i = 0; i < iters; ++i) for (int k = 0; k < 8; ++k) v[k] = __builtin_amdgcn_sqrtf(v[k]); break;
+        default: for (uint32_t i = 0; i < iters; ++i) for (int k = 0; k < 8; ++k) v[k] = __builtin_amdgcn_rcpf(v[k]); break;
+    }
+    out[(uint64_t)blockIdx.x * blockDim.x + threadIdx.x] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+}
+
 // -------------------------------------------------------- constructors ----
 struct CtorZero {
     struct Args { uint64_t unused; };

@@ -877,6 +877,13 @@ int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word,
     return SMMO_OK;
 }
 
+int smmo_valu_probe(float* out, uint32_t kind, uint32_t workgroups, uint32_t iters, void* stream) {
+    if (!out || kind > 3 || workgroups == 0) return fail(SMMO_EINVAL, "valu probe: null output, kind > 3 or no workgroups");
+    k_valu_probe<<<workgroups, 256, 0, S(stream)>>>(out, kind, iters, 1.0000001f);
+    LAUNCH_CHECK("k_valu_probe");
+    return SMMO_OK;
+}
+
 int smmo_check_force_arith(uint32_t lo_bits, uint32_t hi_bits, uint64_t pairs, uint64_t seed, uint64_t* counts_dev,
                            void* stream) {
     if (!counts_dev) return fail(SMMO_EINVAL, "check_force_arith: null output");

@@ -222,3 +222,22 @@ def test_nbody_config_100_steps_against_oracle_goldens():
         assert rel.max() <= 1e-5, f"step {s}: sampled records rel err {rel.max()}"
         assert nbody_hash(*st) == g["sha256"], f"step {s}: state differs from the oracle's (within 1e-5 on the sample)"
     check_heap(sim.heap, expect_live=[golden[last]["count"]])
+
+
+def test_valu_probe_reference_runs_and_checks_arguments():
+    """smmo_valu_probe (the issue-cost reference the bench uses for the force
+    kernel's bound): every kind runs and stores finite values; a kind past 3
+    is refused before any launch."""
+    import ctypes as C
+    from paper_1810_11765_amd import smmo as S
+    say("valu probe")
+    L = S.lib()
+    L.smmo_valu_probe.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p]
+    L.smmo_valu_probe.restype = C.c_int
+    out = torch.full((4 * 256,), float("nan"), dtype=torch.float32, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for kind in range(4):
+        S.check(L.smmo_valu_probe(out.data_ptr(), kind, 4, 100, stream))
+        assert torch.isfinite(out).all()
+    with pytest.raises(S.SmmoError):
+        S.check(L.smmo_valu_probe(out.data_ptr(), 4, 4, 100, stream))
