@@ -60,34 +60,55 @@ __global__ void k_fill_u64(unsigned long long* p, uint64_t n, uint64_t v) {
 // ------------------------------------------- hierarchical enumeration ----
 // Block ids of every set bit of bitmap `bmid`, found through level 1 (Alg. 5 /
 // Sec. 4.1.5: level-0 words whose level-1 bit is clear are never read),
-// appended in any order to R[]; *count must be 0 on entry.  One wave per
-// level-1 word, lane l reading child word 64j + l.  Used for big heaps so that
-// a do-all costs the class's blocks, not the heap's size (Sec. 6.5).
+// appended in any order to R[]; *count must be 0 on entry.  Each wave
+// takes kEnumPerWave consecutive level-1 words (their loads in flight
+// together), lane l reading child word 64j + l of each; a workgroup reserves
+// its range of R with one atomic (the reservations of one counter queue at
+// the memory side, one per arriving request).  Used for big heaps so that a
+// do-all costs the class's blocks, not the heap's size (Sec. 6.5).
+constexpr uint32_t kEnumPerWave = 8;
 __global__ __launch_bounds__(256) void k_enum_blocks(DevHeap h, uint32_t bmid, uint32_t* R,
                                                      unsigned long long* count) {
-    const uint64_t j = global_wave();
-    const uint32_t lane = lane_id();
-    if (j >= h.level_words[1]) return;                    // wave-uniform
-    const uint64_t w1 = *bm_word(h, bmid, 1, j);
-    const uint64_t child = (j << 6) | lane;
-    uint64_t w0 = 0;
-    if ((w1 >> lane) & 1) w0 = *bm_word(h, bmid, 0, child);
-    const uint32_t n = popc64(w0);
+    __shared__ uint32_t wave_total[4];
+    __shared__ unsigned long long wg_base;
+    const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+    const uint64_t nw1 = h.level_words[1];
+    const uint64_t j0 = ((uint64_t)blockIdx.x * 4 + wv) * kEnumPerWave;
+    uint64_t w0[kEnumPerWave];
+    uint32_t n = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kEnumPerWave; ++k) {
+        w0[k] = 0;
+        const uint64_t j = j0 + k;
+        if (j < nw1) {
+            const uint64_t w1 = *bm_word(h, bmid, 1, j);
+            if ((w1 >> lane) & 1) w0[k] = *bm_word(h, bmid, 0, (j << 6) | lane);
+        }
+        n += popc64(w0[k]);
+    }
     uint32_t incl = n;                                    // inclusive prefix of n in the wave
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         uint32_t y = __shfl_up(incl, o, 64);
         if (lane >= (uint32_t)o) incl += y;
     }
-    const uint32_t total = __shfl(incl, 63, 64);
-    if (!total) return;                                   // wave-uniform
-    unsigned long long base = 0;
-    if (lane == 63) base = atomicAdd(count, (unsigned long long)total);
-    base = __shfl(base, 63, 64);
-    uint64_t pos = base + incl - n;
-    while (w0) {
-        R[pos++] = (uint32_t)((child << 6) | ctz64(w0));
-        w0 &= w0 - 1;
+    if (lane == 63) wave_total[wv] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = wave_total[0] + wave_total[1] + wave_total[2] + wave_total[3];
+        wg_base = t ? atomicAdd(count, (unsigned long long)t) : 0;
+    }
+    __syncthreads();
+    uint64_t pos = wg_base + incl - n;
+    for (uint32_t k = 0; k < wv; ++k) pos += wave_total[k];
+#pragma unroll
+    for (uint32_t k = 0; k < kEnumPerWave; ++k) {
+        const uint64_t child = ((j0 + k) << 6) | lane;
+        uint64_t w = w0[k];
+        while (w) {
+            R[pos++] = (uint32_t)((child << 6) | ctz64(w));
+            w &= w - 1;
+        }
     }
 }
 

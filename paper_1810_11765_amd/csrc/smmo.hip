@@ -292,7 +292,8 @@ bool build_block_list(smmo_heap* H, uint32_t cls, hipStream_t s, int* rc) {
     unsigned long long* cnt = scratch_counter(H, 3);
     k_fill_u64<<<1, 64, 0, s>>>(cnt, 1, 0);
     if (hipGetLastError() != hipSuccess) { *rc = fail(SMMO_EHIP, "k_fill_u64 launch"); return false; }
-    k_enum_blocks<<<grid_for(H->hdr.level_words[1], 4), 256, 0, s>>>(H->dev, bm_allocated(cls), scratch_R(H), cnt);
+    k_enum_blocks<<<grid_for(H->hdr.level_words[1], 4 * kEnumPerWave), 256, 0, s>>>(H->dev, bm_allocated(cls),
+                                                                                    scratch_R(H), cnt);
     if (hipGetLastError() != hipSuccess) { *rc = fail(SMMO_EHIP, "k_enum_blocks launch"); return false; }
     H->list_cls = H->stage ? -1 : (int32_t)cls;
     return true;
