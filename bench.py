@@ -340,8 +340,9 @@ def nbody_sub(torch, workloads, steps=2):
     # issue cost of the force kernel's instruction kinds (smmo_valu_probe at 8
     # waves per SIMD): cycles one SIMD spends per wave-instruction, and the
     # force kernel's time if every SIMD issued its instructions back to back
-    # (mix per interaction from the SQ_INSTS_VALU counter run: 30.1 VALU
-    # lane-instructions, one square root and one reciprocal among them)
+    # at those costs (mix per interaction from the SQ_INSTS_VALU counter run:
+    # 30.1 VALU lane-instructions, one square root and one reciprocal among
+    # them, the rest priced as fmac)
     import ctypes as C
     L = S.lib()
     L.smmo_valu_probe.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p]
@@ -349,7 +350,7 @@ def nbody_sub(torch, workloads, steps=2):
     wgs, iters = 2048, 20000
     out = torch.empty(wgs * 256, dtype=torch.float32, device="cuda")
     cyc = {}
-    for kind, name in ((1, "fma"), (2, "sqrt"), (3, "rcp")):
+    for kind, name in ((0, "add"), (1, "fmac"), (2, "sqrt"), (3, "rcp")):
         t = Timer(torch)
         for _ in range(3):
             t.run(name, lambda: S.check(L.smmo_valu_probe(out.data_ptr(), kind, wgs, iters,
@@ -357,7 +358,7 @@ def nbody_sub(torch, workloads, steps=2):
         torch.cuda.synchronize()
         ms = min(t.ms(name))
         cyc[name] = ms * 1e-3 * CLOCK_HZ * SIMDS / (wgs * 4 * iters * 8)
-    per_inter = (30.1 - 2) * cyc["fma"] + cyc["sqrt"] + cyc["rcp"]      # SIMD cycles per wave-interaction
+    per_inter = (30.1 - 2) * cyc["fmac"] + cyc["sqrt"] + cyc["rcp"]     # SIMD cycles per wave-interaction
     bound_ms = inter / 64 * per_inter / (SIMDS * CLOCK_HZ) * 1e3
     return {"bodies_live": n, "ms_per_step": round((sum(tm.ms("merge")) + sum(tm.ms("force")) + sum(tm.ms("move"))) / steps, 3),
             "force_ms": round(f, 3), "merge_ms": round(sum(tm.ms("merge")) / steps, 3),

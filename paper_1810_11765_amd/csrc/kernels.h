@@ -404,16 +404,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_atomic_probe(unsigned long lo
 }
 
 // VALU issue-cost reference (not part of the method): eight independent
-// chains of one instruction kind per lane, `iters` times; kind 0 FP32 add,
-// 1 FP32 fma, 2 hardware square root, 3 hardware reciprocal; the constant
-// operand c comes in a scalar register.  The chains' ends are folded into one
-// store so that nothing is optimized away.
-__global__ __launch_bounds__(256) void k_valu_probe(float* out, uint32_t kind, uint32_t iters, float c) {
+// chains of one instruction kind per lane, `iters` times, all operands in
+// vector registers (the forms the force kernel issues); kind 0 FP32 add,
+// 1 FP32 multiply-add into the chain (fmac), 2 hardware square root,
+// 3 hardware reciprocal.  The chains' ends are folded into one store so that
+// nothing is optimized away.
+__global__ __launch_bounds__(256) void k_valu_probe(float* out, uint32_t kind, uint32_t iters, float c0) {
     float v[8];
     for (int k = 0; k < 8; ++k) v[k] = 1.0f + (float)(threadIdx.x + k) * 0x1p-12f;
+    const float c = c0 + (float)(threadIdx.x % 3) * 0x1p-30f;      // per-lane, so it lives in a vector register
+    const float d = 0x1p-20f * c;
     switch (kind) {
         case 0: for (uint32_t i = 0; i < iters; ++i) for (int k = 0; k < 8; ++k) v[k] = v[k] + c; break;
-        case 1: for (uint32_t i = 0; i < iters; ++i) for (int k = 0; k < 8; ++k) v[k] = __builtin_fmaf(v[k], c, c); break;
+        case 1: for (uint32_t i = 0; i < iters; ++i) for (int k = 0; k < 8; ++k) v[k] = __builtin_fmaf(c, d, v[k]); break;
         case 2: for (uint32_t i = 0; i < iters; ++i) for (int k = 0; k < 8; ++k) v[k] = __builtin_amdgcn_sqrtf(v[k]); break;
         default: for (uint32_t i = 0; i < iters; ++i) for (int k = 0; k < 8; ++k) v[k] = __builtin_amdgcn_rcpf(v[k]); break;
     }
