@@ -179,23 +179,30 @@ def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bo
 
 
 def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instances: int = 256,
-          wg_per_cu: int = 0, lookups: int = 5, steps_per_tick: int = 10, block_objects: int = 64):
+          wg_per_cu: int = 0, lookups: int = 5, steps_per_tick: int = 10, block_objects: int = 64,
+          tick_s: float = 0.0):
     """Continuous batching over arrivals (arrival times scaled by time_scale):
     between launches, arrived requests are admitted while the arena has room;
     each launch advances every live instance by up to `steps_per_tick` steps
     (one persistent-kernel launch on wg_per_cu workgroups per CU, 0 = all that
-    fit); finished instances leave and free their memory.
+    fit); finished instances leave and free their memory.  With tick_s > 0 a
+    launch starts at most every tick_s seconds (a batching window: instances
+    wait for the next tick, so each launch carries more of them, for fewer
+    GPU-seconds and a longer time to completion); 0 launches back to back
+    while anything is live.
 
     Returns dict with results per request, per instance-step latencies (ms:
     the launch's GPU time over its steps, one entry per live instance and
-    step), wall seconds, busy seconds (GPU time of the launches), the mean
-    number of live instances per step run, admission host times (ms, outside
-    the latencies) and admission delays."""
+    step), per-request completion times (s, arrival to finished), wall
+    seconds, busy seconds (GPU time of the launches), the mean number of live
+    instances per step run, admission host times (ms, outside the latencies)
+    and admission delays."""
     fleet = Fleet(arena, max(1, min(max_instances, len(reqs))), lookups=lookups, block_objects=block_objects)
     fleet.batch.set_grid(wg_per_cu)
     pending = deque(sorted(reqs, key=lambda r: r.arrival))
-    lat, admit_delay, admit_ms, results = [], [], [], {}
+    lat, admit_delay, admit_ms, done_s, results = [], [], [], [], {}
     busy, steps_run = 0.0, 0
+    next_tick = 0.0
     t0 = time.perf_counter()
     while pending or fleet.live:
         now = time.perf_counter() - t0
@@ -208,7 +215,8 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
             admit_ms.append((time.perf_counter() - ta) * 1e3)
             admit_delay.append(now - pending[0].arrival * time_scale)
             pending.popleft()
-        if fleet.live:
+        if fleet.live and now >= next_tick:
+            next_tick = now + tick_s
             k = min(steps_per_tick, min(fleet.left.values()))      # stop when the first instance ends
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
@@ -219,12 +227,18 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
             busy += ms * 1e-3
             steps_run += k
             lat.extend([ms / k] * (len(fleet.live) * k))
-            for req, st, status in fleet.harvest():
+            finished = fleet.harvest()
+            t_done = time.perf_counter() - t0
+            for req, st, status in finished:
                 results[req.rid] = (st, status)
-        elif pending:
-            time.sleep(max(0.0, pending[0].arrival * time_scale - (time.perf_counter() - t0)))
+                done_s.append(t_done - req.arrival * time_scale)
+        else:
+            wake = next_tick if fleet.live else float("inf")
+            if pending and pending[0].arrival * time_scale > now:       # (an arrived one waits for memory)
+                wake = min(wake, pending[0].arrival * time_scale)
+            time.sleep(max(0.0, wake - (time.perf_counter() - t0)))
     wall = time.perf_counter() - t0
     fleet.close()
     return {"results": results, "latency_ms": np.array(lat), "wall_s": wall, "busy_s": busy,
-            "mean_live": len(lat) / max(1, steps_run),
+            "mean_live": len(lat) / max(1, steps_run), "completion_s": np.array(done_s),
             "admit_ms": np.array(admit_ms), "admit_delay_s": np.array(admit_delay)}

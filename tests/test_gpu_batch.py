@@ -120,6 +120,21 @@ def test_serving_continuous_admission_matches_oracle():
     assert out["latency_ms"].min() > 0
 
 
+def test_serving_with_a_batching_window_matches_oracle():
+    """Launches at most every 10 ms: instances wait for the tick, results and
+    step counts are unchanged, every request reports its completion time, and
+    a request never completes before its steps could have run."""
+    say("serve window")
+    sv = SV()
+    reqs = sv.make_requests(seed=12, count=12, lo=16, hi=96)
+    arena = S().Arena(sv.arena_bytes_for(reqs))
+    out = sv.serve(reqs, 30, arena, time_scale=0.05, steps_per_tick=10, tick_s=0.01)
+    _check(out["results"], reqs, 30)
+    assert len(out["latency_ms"]) == 12 * 30
+    assert len(out["completion_s"]) == 12
+    assert out["completion_s"].min() >= 0.015                 # 3 launches, at least 2 ticks apart
+
+
 def test_serving_waits_for_memory():
     """An arena that holds only a few instances at once: later requests wait
     for earlier ones to leave, and all results still match."""
