@@ -597,9 +597,10 @@ int smmo_atomic_probe(uint64_t* words, uint64_t nwords, uint32_t lanes_per_word,
 
 /* VALU issue-cost reference for the n-body force kernel (not part of the
  * method): `workgroups` workgroups of 256 threads each run eight independent
- * chains of `iters` instructions of one kind per lane (kind 0: FP32 add,
- * 1: FP32 fma, 2: hardware square root, 3: hardware reciprocal) and store one
- * float per thread into out (a device array of workgroups * 256 floats).
+ * chains of `iters` instructions of one kind per lane, all operands in
+ * vector registers (kind 0: FP32 add, 1: FP32 multiply-add into the chain,
+ * 2: hardware square root, 3: hardware reciprocal) and store one float per
+ * thread into out (a device array of workgroups * 256 floats).
  * Time it with events: wave-instructions = workgroups * 4 * iters * 8.
  * kind > 3, workgroups 0 or a null out: SMMO_EINVAL.  Asynchronous. */
 int smmo_valu_probe(float* out, uint32_t kind, uint32_t workgroups, uint32_t iters, void* stream);
