@@ -320,7 +320,9 @@ def nbody_sub(torch, workloads, steps=2):
     `steps` steps after one warm-up step; interactions/s of the all-pairs
     force (device_do) and its FP32 rate at 14 flops per interaction (the
     correctly rounded sqrt and division counted as one flop each) against the
-    157.3 TFLOP/s vector peak."""
+    157.3 TFLOP/s vector peak; and the force's issue bound: the VALU issue
+    cost of its instruction kinds measured by smmo_valu_probe, applied to its
+    instruction mix."""
     from paper_1810_11765_amd import smmo as S
     nb = workloads.NBody(seed=42)
     nb.populate()
