@@ -452,7 +452,8 @@ def sweep_sub(torch, nblocks):
 
 def batch_sub(torch, steps=200, count=256):
     """Predator-prey instances of log-uniform side in [64, 1024): plain (one by
-    one, per-phase launches) vs batched (persistent kernel, graph replay) vs
+    one, per-phase launches) vs batched (one launch per phase for every
+    instance, or one persistent kernel; graph replay) vs
     served (Poisson arrivals at 50/s, continuous admission; again with
     batching windows of 20 and 50 ms, and with the arrivals 10x and 100x
     faster).
@@ -466,7 +467,7 @@ def batch_sub(torch, steps=200, count=256):
     inst_steps = count * steps
     # launch shape found by the autotuner for this workload on this device
     # (bench.py --suite autotune), if the package holds one
-    tuned = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5, "block_objects": 64}
+    tuned = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5, "block_objects": 64, "mode": S.BATCH_PHASED}
     tuned.update(tune.load(TUNED_LAUNCH, "predator-prey batched %d instances %d steps" % (count, steps)) or {})
     if tuned["block_objects"] != 64:
         del arena
@@ -475,19 +476,25 @@ def batch_sub(torch, steps=200, count=256):
     base, t_base, grid_base = sv.run_batched(reqs, steps, arena, per_launch=1, graph=True)
     batched, t_batch, grid = sv.run_batched(reqs, steps, arena, per_launch=tuned["steps_per_launch"], graph=True,
                                             wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"],
-                                            block_objects=tuned["block_objects"])
+                                            block_objects=tuned["block_objects"], mode=tuned["mode"])
+    # the other batch form at its best measured shape (10 steps per launch)
+    other_mode = 1 - tuned["mode"]
+    other, t_other, grid_other = sv.run_batched(reqs, steps, arena, per_launch=10, graph=True, mode=other_mode,
+                                                block_objects=tuned["block_objects"])
     served = sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"],
-                      steps_per_tick=tuned["steps_per_launch"], block_objects=tuned["block_objects"])
+                      steps_per_tick=tuned["steps_per_launch"], block_objects=tuned["block_objects"],
+                      mode=tuned["mode"])
     # the same requests arriving 10x and 100x faster: more instances live at
     # once, so each launch has more work for the same step latency
     faster = {ts: sv.serve(reqs, steps, arena, time_scale=ts, wg_per_cu=tuned["wg_per_cu"],
                            lookups=tuned["lookups"], steps_per_tick=tuned["steps_per_launch"],
-                           block_objects=tuned["block_objects"]) for ts in (0.1, 0.01)}
+                           block_objects=tuned["block_objects"], mode=tuned["mode"]) for ts in (0.1, 0.01)}
     # config 5's arrivals again, with batching windows of 20 and 50 ms between launches
     windowed = {w: sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"],
-                            steps_per_tick=tuned["steps_per_launch"], block_objects=tuned["block_objects"], tick_s=w)
+                            steps_per_tick=tuned["steps_per_launch"], block_objects=tuned["block_objects"], tick_s=w,
+                            mode=tuned["mode"])
                 for w in (0.02, 0.05)}
-    runs = ([batched, base, served["results"]] + [f["results"] for f in windowed.values()] +
+    runs = ([batched, base, other, served["results"]] + [f["results"] for f in windowed.values()] +
             [f["results"] for f in faster.values()])
     same = all(all(all(np.array_equal(a, b) for a, b in zip(plain[r.rid][0], run[r.rid][0])) for run in runs)
                for r in reqs)
@@ -503,6 +510,8 @@ def batch_sub(torch, steps=200, count=256):
             "batched_launch_shape": dict(tuned, workgroups=grid),
             "batched_default_shape_steps_s": round(inst_steps / t_base, 1),
             "batched_default_workgroups": grid_base,
+            "batched_other_form": {"mode": ("phased", "persistent")[other_mode], "steps_per_launch": 10,
+                                   "steps_s": round(inst_steps / t_other, 1), "workgroups": grid_other},
             "batched_over_plain": round(t_plain / t_batch, 2),
             "served_wall_s": round(served["wall_s"], 3), "served_busy_s": round(served["busy_s"], 3),
             "served_steps_s": round(inst_steps / served["wall_s"], 1),
@@ -688,9 +697,8 @@ def heap_size_suite(torch, workloads, steps):
 
 def autotune_suite(torch, workloads, cache):
     """The autotuner (paper_1810_11765_amd/tune.py) on four workloads:
-    the batched predator-prey form of config 5 (workgroups per CU of the
-    persistent kernel, steps per launch, active-block lookups r, objects
-    per block), predator-prey 1024 x 1024 with per-phase launches (objects
+    the batched predator-prey form of config 5 (batch form, workgroups per
+    CU, steps per launch, active-block lookups r, objects per block), predator-prey 1024 x 1024 with per-phase launches (objects
     per block, r, do-all grid cap and unit count), the Life-like step (r,
     do-all grid cap and unit count) and the 2^21-block sweep (grid and
     blocks in flight).  Every candidate's result is compared with the
@@ -711,14 +719,15 @@ def autotune_suite(torch, workloads, cache):
         _progress("autotune batched", cfg)
         res, dt, grid = sv.run_batched(reqs, 200, arena, per_launch=cfg["steps_per_launch"], graph=True,
                                        wg_per_cu=cfg["wg_per_cu"], lookups=cfg["lookups"],
-                                       block_objects=cfg["block_objects"])
+                                       block_objects=cfg["block_objects"], mode=cfg["mode"])
         return dt, res
 
     def same_states(a, b):
         return all(all(np.array_equal(x, y) for x, y in zip(a[k][0], b[k][0])) and a[k][1] == b[k][1] == 0
                    for k in a)
-    rec = tune.search(batched, {"wg_per_cu": [0, 1, 2, 3], "steps_per_launch": [1, 2, 5, 10],
-                                "lookups": [5, 3, 8, 12], "block_objects": [64, 32]}, reps=2, equal=same_states)
+    rec = tune.search(batched, {"mode": [S.BATCH_PHASED, S.BATCH_PERSISTENT], "wg_per_cu": [0, 1, 2, 3],
+                                "steps_per_launch": [1, 2, 5, 10], "lookups": [5, 3, 8, 12],
+                                "block_objects": [64, 32]}, reps=2, equal=same_states)
     tune.save(cache, "predator-prey batched 256 instances 200 steps", rec)
     out["batched"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}
     out["batched"]["rejected"] = sum(not t["same_result"] for t in rec["trials"])

@@ -508,10 +508,18 @@ int smmo_arena_free(smmo_arena* arena, void* dev_ptr);
 int smmo_arena_stats(const smmo_arena* arena, uint64_t* free_bytes, uint64_t* largest_free);
 
 /* A batch advances many independent predator-prey instances (each its own
- * heap and grids, see smmo_wator_args) with ONE persistent kernel launch per
- * call: each instance gets a share of the workgroups proportional to its
- * grid, and its four phases per step are separated by barriers among its own
- * workgroups only.  The batch's device tables live in `arena`. */
+ * heap and grids, see smmo_wator_args) together: each instance gets a share
+ * of the workgroups proportional to its grid (at most one wave per block of
+ * its heap), in one of two forms (smmo_batch_set_mode):
+ *  SMMO_BATCH_PHASED (default): one launch per phase of a step (fish plan,
+ *    fish move, shark plan, shark move) for every instance at once; the
+ *    kernel boundaries separate the phases.
+ *  SMMO_BATCH_PERSISTENT: ONE persistent kernel launch per call for all the
+ *    call's steps; an instance's four phases per step are separated by
+ *    barriers among its own workgroups only (every workgroup resident).
+ * Both give the same results.  The batch's device tables live in `arena`. */
+#define SMMO_BATCH_PHASED 0u
+#define SMMO_BATCH_PERSISTENT 1u
 typedef struct smmo_batch smmo_batch;
 int smmo_batch_create(smmo_arena* arena, uint32_t max_instances, smmo_batch** out);
 int smmo_batch_destroy(smmo_batch* batch);     /* returns its tables to the arena */
@@ -528,8 +536,8 @@ int smmo_batch_remove(smmo_batch* batch, uint32_t slot);
  * smmo_batch_capture_graph, which uploads before it captures).  Calls on one
  * batch must use one stream at a time. */
 int smmo_batch_step(smmo_batch* batch, uint32_t steps, void* stream);
-/* Capture `launches` persistent-kernel launches of `steps_per_launch` steps
- * each (the work of that many smmo_batch_step calls) into a HIP graph and
+/* Capture `launches` launch groups of `steps_per_launch` steps each (the
+ * work of that many smmo_batch_step calls) into a HIP graph and
  * instantiate it: the alloc -> do-all -> dealloc step of every admitted
  * instance, replayed with one graph launch (Sec. 2.1's do-alls, batched).
  * `stream` must be a created stream (not the null stream); nothing runs during
@@ -538,7 +546,8 @@ int smmo_batch_step(smmo_batch* batch, uint32_t steps, void* stream);
  * captured kernels read the batch's tables at replay time, so a graph may be
  * replayed only while the batch keeps the instance set and grid it was
  * captured with: smmo_batch_graph_launch refuses it (SMMO_EINVAL) after
- * smmo_batch_add_wator, smmo_batch_remove or smmo_batch_set_grid.  Each replay
+ * smmo_batch_add_wator, smmo_batch_remove, smmo_batch_set_grid or
+ * smmo_batch_set_mode.  Each replay
  * advances every instance by min(launches * steps_per_launch, its remaining
  * steps).  The graph holds no device memory of its own besides what the HIP
  * runtime keeps for an instantiated graph; free it with
@@ -552,12 +561,17 @@ int smmo_batch_graph_destroy(smmo_batch_graph* graph);
 /* Remaining steps of every slot (0xFFFFFFFF for an empty slot), to host
  * memory of max_instances entries.  Synchronizes. */
 int smmo_batch_remaining(smmo_batch* batch, uint32_t* out, void* stream);
-/* Workgroups of the persistent kernel (the occupancy-bounded grid). */
+/* Workgroups of the batch's launches (the occupancy-bounded grid of the
+ * current mode). */
 int smmo_batch_grid(const smmo_batch* batch, uint32_t* workgroups);
-/* Use wg_per_cu workgroups per CU for the persistent kernel (0: as many as
- * can be resident, the default); more than can be resident is capped.  The
- * schedule is rebuilt at the next step.  Results do not depend on it. */
+/* Use wg_per_cu workgroups per CU (0: as many as can be resident, the
+ * default); more than can be resident is capped.  The schedule is rebuilt at
+ * the next step.  Results do not depend on it. */
 int smmo_batch_set_grid(smmo_batch* batch, uint32_t wg_per_cu);
+/* SMMO_BATCH_PHASED or SMMO_BATCH_PERSISTENT (SMMO_EINVAL otherwise); the
+ * grid follows the mode's occupancy and the schedule is rebuilt at the next
+ * step.  Results do not depend on it. */
+int smmo_batch_set_mode(smmo_batch* batch, uint32_t mode);
 
 /* ------------------------------------------------------ launch shape ---- */
 

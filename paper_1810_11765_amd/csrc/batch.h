@@ -26,11 +26,12 @@ struct BatchProg {          // device-updated progress
 };
 struct BatchSched {         // host-written schedule
     uint32_t wg_begin, wg_count;
+    uint32_t unit_log2;     // a phase's unit of work: 1 << unit_log2 consecutive block bits
+    uint32_t pad;
 };
 
 constexpr uint32_t kBarrierSpin = 1u << 24;
-constexpr uint32_t kBatchUnit = 8;                        // blocks per unit of work in a phase
-constexpr uint64_t kUnitMask = (1ull << kBatchUnit) - 1;
+constexpr uint32_t kBatchUnitLog2Max = 3;                 // at most 8 blocks per unit of work in a phase
 
 // Barrier among the workgroups of one instance, a two-level tree: each
 // workgroup arrives at the counter of its group of kBarGroup workgroups (a
@@ -91,29 +92,33 @@ __device__ inline void instance_barrier(uint32_t* bar, uint32_t number, uint32_t
 }
 
 // One phase of one instance, spread over the instance's waves; units of
-// kBatchUnit block bits of allocated[cls].  With `snap`, each visited block's iteration
+// 1 << unit_log2 block bits of allocated[cls] (the host picks the size per
+// instance: 8 when its waves are few for its heap, down to 1 when it has
+// waves to spare, so that a lone instance's blocks are not visited one after
+// the other by a few waves).  With `snap`, each visited block's iteration
 // word is set from its allocation word after the method ran (the method of a
 // plan phase neither creates nor destroys objects of the class).
 template <class M>
 __device__ inline void batch_phase(const DevHeap& h, uint32_t cls, const smmo_wator_args& a, uint32_t wave_rank,
-                                   uint32_t nwaves, bool snap) {
+                                   uint32_t nwaves, uint32_t unit_log2, bool snap) {
     const uint32_t lane = lane_id();
     const uint64_t* l0 = bm_word(h, bm_allocated(cls), 0, 0);
     const uint64_t valid = ~h.cls_pad[cls];
-    constexpr uint32_t kPerWord = 64 / kBatchUnit;
-    const uint64_t nunits = h.level_words[0] * kPerWord;
+    const uint32_t span = 1u << unit_log2, per_word_log2 = 6 - unit_log2;
+    const uint64_t unit_mask = (1ull << span) - 1;
+    const uint64_t nunits = h.level_words[0] << per_word_log2;
     const typename M::Prep prep = M::prepare(h, cls, a);
     for (uint64_t u = wave_rank; u < nunits; u += nwaves) {
-        const uint64_t w = u / kPerWord;
-        const uint32_t first = (uint32_t)(u % kPerWord) * kBatchUnit;
+        const uint64_t w = u >> per_word_log2;
+        const uint32_t first = (uint32_t)(u & ((1u << per_word_log2) - 1)) << unit_log2;
         const uint64_t my_blk = (w << 6) + first + lane;
-        const bool mine = lane < kBatchUnit && my_blk < h.M;
+        const bool mine = lane < span && my_blk < h.M;
         uint64_t my_word = 0, word;
         if (!M::kSnapshot) {       // no block of the class appears during a plan phase
             if (mine) my_word = at_load(&h.alloc[my_blk]);
-            word = at_load(l0 + w) & (kUnitMask << first);
+            word = at_load(l0 + w) & (unit_mask << first);
         } else {
-            word = at_load(l0 + w) & (kUnitMask << first);
+            word = at_load(l0 + w) & (unit_mask << first);
             if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
         }
         while (word) {
@@ -146,19 +151,50 @@ __global__ __launch_bounds__(256) void k_batch_wator(BatchDesc* desc, BatchProg*
     for (uint32_t s = 0; s < todo; ++s) {
         smmo_wator_args a = D.a;
         a.step = (int32_t)(done0 + s + 1);
-        batch_phase<MFishPlan>(D.h, a.fish_cls, a, wave_rank, nwaves, true);
+        batch_phase<MFishPlan>(D.h, a.fish_cls, a, wave_rank, nwaves, S.unit_log2, true);
         instance_barrier(bar, ++nbar, r, S.wg_count, D.h.status);
-        batch_phase<MFishMove>(D.h, a.fish_cls, a, wave_rank, nwaves, false);
+        batch_phase<MFishMove>(D.h, a.fish_cls, a, wave_rank, nwaves, S.unit_log2, false);
         instance_barrier(bar, ++nbar, r, S.wg_count, D.h.status);
-        batch_phase<MSharkPlan>(D.h, a.shark_cls, a, wave_rank, nwaves, true);
+        batch_phase<MSharkPlan>(D.h, a.shark_cls, a, wave_rank, nwaves, S.unit_log2, true);
         instance_barrier(bar, ++nbar, r, S.wg_count, D.h.status);
-        batch_phase<MSharkMove>(D.h, a.shark_cls, a, wave_rank, nwaves, false);
+        batch_phase<MSharkMove>(D.h, a.shark_cls, a, wave_rank, nwaves, S.unit_log2, false);
         instance_barrier(bar, ++nbar, r, S.wg_count, D.h.status);
     }
     if (r == 0 && threadIdx.x == 0) {
         prog[i].remaining -= todo;
         prog[i].done = done0 + todo;
     }
+}
+
+// Phased form: one phase of step s of every admitted instance per launch;
+// the kernel boundaries separate the phases, so no instance barrier is
+// needed, and each phase's kernel holds only its own method (fewer registers,
+// more waves per SIMD than the persistent kernel, which holds all four).
+template <class M, bool kShark, bool kSnap>
+__global__ __launch_bounds__(256) void k_batch_phase(const BatchDesc* __restrict__ desc,
+                                                      const BatchProg* __restrict__ prog,
+                                                      const BatchSched* __restrict__ sched,
+                                                      const int32_t* __restrict__ wg_inst, uint32_t s) {
+    const int32_t i = wg_inst[blockIdx.x];
+    if (i < 0) return;                                            // idle workgroup (uniform)
+    const BatchProg P = prog[i];
+    if (s >= P.remaining) return;                                 // the instance has finished
+    const BatchDesc& D = desc[i];
+    const BatchSched S = sched[i];
+    const uint32_t r = blockIdx.x - S.wg_begin;
+    const uint32_t wave_rank = r * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwaves = S.wg_count * (blockDim.x >> 6);
+    smmo_wator_args a = D.a;
+    a.step = (int32_t)(P.done + s + 1);
+    batch_phase<M>(D.h, kShark ? a.shark_cls : a.fish_cls, a, wave_rank, nwaves, S.unit_log2, kSnap);
+}
+// after a phased launch group of `steps` steps: every slot's progress
+__global__ void k_batch_advance(BatchProg* prog, uint32_t n, uint32_t steps) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t todo = steps < prog[i].remaining ? steps : prog[i].remaining;
+    prog[i].remaining -= todo;
+    prog[i].done += todo;
 }
 
 }  // namespace smmo

@@ -1097,7 +1097,10 @@ struct smmo_batch {
     uint32_t max_inst;
     uint32_t grid;                              // persistent workgroups in use
     uint32_t grid_max;                          // all that can be resident (tables sized for it)
-    uint32_t cus, per_cu;                       // compute units, resident workgroups per CU
+    uint32_t cus, per_cu;                       // compute units, resident workgroups per CU (current mode)
+    uint32_t per_cu_mode[2];                    // resident workgroups per CU of each mode's kernels
+    uint32_t mode;                              // SMMO_BATCH_PHASED or SMMO_BATCH_PERSISTENT
+    uint32_t wg_req = 0;                        // requested workgroups per CU (0: all resident)
     uint8_t* dev;                               // device tables (from the arena)
     BatchDesc* d_desc;
     BatchProg* d_prog;
@@ -1107,6 +1110,7 @@ struct smmo_batch {
     std::vector<int> used;                      // slot in use
     std::vector<uint64_t> weight;               // grid cells of each slot
     std::vector<uint32_t> cap;                  // most workgroups a slot's instance can use
+    std::vector<uint64_t> w0;                   // level-0 bitmap words of a slot's heap
     uint8_t* h_stage = nullptr;                 // pinned staging of the schedule tables
     hipEvent_t stage_done = nullptr;            // the last upload from the staging has completed
     bool dirty;
@@ -1195,16 +1199,30 @@ int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
     int dev = 0, cus = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu_phased = 0;
+    {
+        int o[4];
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o[0], (k_batch_phase<MFishPlan, false, true>), 256, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o[1], (k_batch_phase<MFishMove, false, false>), 256, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o[2], (k_batch_phase<MSharkPlan, true, true>), 256, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o[3], (k_batch_phase<MSharkMove, true, false>), 256, 0));
+        per_cu_phased = std::min(std::min(o[0], o[1]), std::min(o[2], o[3]));
+    }
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_wator, 256, 0));
-    if (per_cu < 1) return fail(SMMO_EHIP, "batch kernel cannot be resident");
+    if (per_cu < 1 || per_cu_phased < 1) return fail(SMMO_EHIP, "batch kernels cannot be resident");
     smmo_batch* B = new smmo_batch();
     B->arena = arena;
     B->max_inst = max_inst;
-    // every workgroup must be resident at once for the instance barriers: the
-    // grid is the occupancy the runtime reports for this kernel (capped)
+    // the persistent kernel needs every workgroup resident at once for the
+    // instance barriers: each mode's grid is the occupancy the runtime reports
+    // for its kernels; the tables are sized for the larger
     B->cus = (uint32_t)cus;
-    B->per_cu = (uint32_t)per_cu;
-    B->grid_max = B->grid = (uint32_t)cus * (uint32_t)per_cu;
+    B->per_cu_mode[SMMO_BATCH_PHASED] = (uint32_t)per_cu_phased;
+    B->per_cu_mode[SMMO_BATCH_PERSISTENT] = (uint32_t)per_cu;
+    B->mode = SMMO_BATCH_PHASED;
+    B->per_cu = B->per_cu_mode[B->mode];
+    B->grid = (uint32_t)cus * B->per_cu;
+    B->grid_max = (uint32_t)cus * (uint32_t)std::max(per_cu, per_cu_phased);
     const uint64_t bytes = align_up(sizeof(BatchDesc) * max_inst, 256) + align_up(sizeof(BatchProg) * max_inst, 256) +
                            align_up(sizeof(BatchSched) * max_inst, 256) + align_up(4ull * B->grid_max, 256) +
                            align_up(4ull * max_inst * bar_words(B->grid_max), 256);
@@ -1221,6 +1239,7 @@ int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
     B->used.assign(max_inst, 0);
     B->weight.assign(max_inst, 0);
     B->cap.assign(max_inst, 0);
+    B->w0.assign(max_inst, 0);
     {
         void* hp = nullptr;
         const uint64_t stage_bytes = sizeof(BatchSched) * max_inst + 4ull * B->grid_max;
@@ -1278,8 +1297,9 @@ int smmo_batch_add_wator(smmo_batch* B, smmo_heap* heap, const smmo_wator_args* 
     heap->list_cls = -1;
     B->used[slot] = 1;
     B->weight[slot] = (uint64_t)args->width * (uint64_t)args->height;
-    // one wave per unit of the instance's heap (kBatchUnit blocks, batch.h) at most
-    B->cap[slot] = (uint32_t)std::max<uint64_t>(1, (heap->hdr.num_blocks + 4 * kBatchUnit - 1) / (4 * kBatchUnit));
+    // one wave per block of the instance's heap at most (units of one block)
+    B->cap[slot] = (uint32_t)std::max<uint64_t>(1, (heap->hdr.num_blocks + 3) / 4);
+    B->w0[slot] = heap->hdr.level_words[0];
     B->dirty = true;
     ++B->generation;
     *slot_out = slot;
@@ -1309,7 +1329,7 @@ static int batch_schedule(smmo_batch* B, hipStream_t s) {
     uint64_t total = 0;
     uint32_t n = 0;
     for (uint32_t i = 0; i < B->max_inst; ++i) {
-        sched[i] = BatchSched{0, 0};
+        sched[i] = BatchSched{0, 0, 0, 0};
         if (B->used[i]) { total += B->weight[i]; ++n; }
     }
     if (n > B->grid) return fail(SMMO_EINVAL, "batch: %u instances but only %u workgroups", n, B->grid);
@@ -1319,7 +1339,11 @@ static int batch_schedule(smmo_batch* B, hipStream_t s) {
         if (!B->used[i]) continue;
         const uint32_t extra = total ? (uint32_t)((double)spare * (double)B->weight[i] / (double)total) : 0;
         const uint32_t cnt = std::min(1 + extra, std::max(1u, B->cap[i]));
-        sched[i] = BatchSched{next, cnt};
+        // the coarsest unit (at most 8 blocks) that still gives every wave
+        // of the instance four units of its heap to take
+        uint32_t ul = kBatchUnitLog2Max;
+        while (ul > 0 && (B->w0[i] << (6 - ul)) < 4ull * 4 * cnt) --ul;
+        sched[i] = BatchSched{next, cnt, ul, 0};
         for (uint32_t k = 0; k < cnt; ++k) wg[next + k] = (int32_t)i;
         next += cnt;
     }
@@ -1330,9 +1354,27 @@ static int batch_schedule(smmo_batch* B, hipStream_t s) {
     return SMMO_OK;
 }
 
-// One persistent launch: the instance barrier counters are cleared by a
-// kernel (not a memset, so the pair can be captured and replayed).
+// The launches of one group of `steps` steps, in the batch's mode.
 static int batch_launch(smmo_batch* B, uint32_t steps, hipStream_t s) {
+    if (B->mode == SMMO_BATCH_PHASED) {
+        // one launch per phase of each step; the boundaries order the phases
+        for (uint32_t st = 0; st < steps; ++st) {
+            k_batch_phase<MFishPlan, false, true><<<B->grid, 256, 0, s>>>(B->d_desc, B->d_prog, B->d_sched,
+                                                                          B->d_wg_inst, st);
+            k_batch_phase<MFishMove, false, false><<<B->grid, 256, 0, s>>>(B->d_desc, B->d_prog, B->d_sched,
+                                                                           B->d_wg_inst, st);
+            k_batch_phase<MSharkPlan, true, true><<<B->grid, 256, 0, s>>>(B->d_desc, B->d_prog, B->d_sched,
+                                                                          B->d_wg_inst, st);
+            k_batch_phase<MSharkMove, true, false><<<B->grid, 256, 0, s>>>(B->d_desc, B->d_prog, B->d_sched,
+                                                                           B->d_wg_inst, st);
+        }
+        LAUNCH_CHECK("k_batch_phase");
+        k_batch_advance<<<grid_for(B->max_inst, 256), 256, 0, s>>>(B->d_prog, B->max_inst, steps);
+        LAUNCH_CHECK("k_batch_advance");
+        return SMMO_OK;
+    }
+    // one persistent launch: the instance barrier counters are cleared by a
+    // kernel (not a memset, so the pair can be captured and replayed)
     const uint32_t stride = bar_words(B->grid_max);
     const uint64_t bar_u64 = ((uint64_t)B->max_inst * stride + 1) / 2;
     k_fill_u64<<<grid_for(bar_u64, 256), 256, 0, s>>>(reinterpret_cast<unsigned long long*>(B->d_bar), bar_u64, 0);
@@ -1416,11 +1458,20 @@ int smmo_batch_grid(const smmo_batch* B, uint32_t* workgroups) {
 
 int smmo_batch_set_grid(smmo_batch* B, uint32_t wg_per_cu) {
     if (!B) return fail(SMMO_EINVAL, "null batch");
+    B->wg_req = wg_per_cu;
     const uint32_t w = wg_per_cu == 0 || wg_per_cu > B->per_cu ? B->per_cu : wg_per_cu;
     B->grid = B->cus * w;
     B->dirty = true;
     ++B->generation;
     return SMMO_OK;
+}
+
+int smmo_batch_set_mode(smmo_batch* B, uint32_t mode) {
+    if (!B) return fail(SMMO_EINVAL, "null batch");
+    if (mode != SMMO_BATCH_PHASED && mode != SMMO_BATCH_PERSISTENT) return fail(SMMO_EINVAL, "batch: unknown mode %u", mode);
+    B->mode = mode;
+    B->per_cu = B->per_cu_mode[mode];
+    return smmo_batch_set_grid(B, B->wg_req);
 }
 
 uint64_t smmo_ref_make(uint32_t cls, uint64_t block, uint32_t slot) { return make_ref(cls, block, slot); }

@@ -5,9 +5,10 @@ grids carved from one arena):
 
 * plain      one instance after the other through the per-phase C-ABI calls
              (four do-alls and two snapshots per step, one launch each);
-* batched    all instances admitted up front, every step one persistent
-             kernel launch for all of them (smmo_batch_step), optionally
-             replayed from a captured HIP graph;
+* batched    all instances admitted up front, every step advanced for all of
+             them at once (smmo_batch_step: one launch per phase, or one
+             persistent launch for several steps), optionally replayed from
+             a captured HIP graph;
 * served     continuous batching: requests arrive over time (Poisson), are
              admitted between steps when the arena has room for their heap
              and grids, advance together with whatever else is running, and
@@ -68,9 +69,11 @@ class Fleet:
     remaining)), so finding finished instances needs no device readback; the
     device's own count is checked once, when an instance leaves."""
 
-    def __init__(self, arena: S.Arena, max_instances: int = 256, lookups: int = 5, block_objects: int = 64):
+    def __init__(self, arena: S.Arena, max_instances: int = 256, lookups: int = 5, block_objects: int = 64,
+                 mode: int = S.BATCH_PHASED):
         self.arena = arena
         self.batch = S.Batch(arena, max_instances)
+        self.batch.set_mode(mode)
         self.lookups = lookups              # active-block lookups r of every instance heap
         self.block_objects = block_objects  # objects per block of the smallest class (layout)
         self.live = {}                      # slot -> (request, WaTor)
@@ -143,12 +146,13 @@ def run_plain(reqs, steps: int, arena: S.Arena, block_objects: int = 64):
 
 
 def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bool = False, wg_per_cu: int = 0,
-                lookups: int = 5, block_objects: int = 64):
-    """All instances admitted, then `steps` steps of the persistent kernel
-    (`per_launch` steps per launch, wg_per_cu workgroups per CU, 0 = all that
-    fit; `lookups` active-block lookups per allocation).  Returns (results,
-    seconds of the stepping, grid workgroups)."""
-    fleet = Fleet(arena, max(len(reqs), 1), lookups=lookups, block_objects=block_objects)
+                lookups: int = 5, block_objects: int = 64, mode: int = S.BATCH_PHASED):
+    """All instances admitted, then `steps` steps of the batch (`per_launch`
+    steps per smmo_batch_step call, wg_per_cu workgroups per CU, 0 = all that
+    fit; `lookups` active-block lookups per allocation; `mode` phased or
+    persistent).  Returns (results, seconds of the stepping, grid
+    workgroups)."""
+    fleet = Fleet(arena, max(len(reqs), 1), lookups=lookups, block_objects=block_objects, mode=mode)
     fleet.batch.set_grid(wg_per_cu)
     for r in reqs:
         assert fleet.admit(r, steps), "arena too small for the whole batch"
@@ -180,12 +184,12 @@ def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bo
 
 def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instances: int = 256,
           wg_per_cu: int = 0, lookups: int = 5, steps_per_tick: int = 10, block_objects: int = 64,
-          tick_s: float = 0.0):
+          tick_s: float = 0.0, mode: int = S.BATCH_PHASED):
     """Continuous batching over arrivals (arrival times scaled by time_scale):
     between launches, arrived requests are admitted while the arena has room;
-    each launch advances every live instance by up to `steps_per_tick` steps
-    (one persistent-kernel launch on wg_per_cu workgroups per CU, 0 = all that
-    fit); finished instances leave and free their memory.  With tick_s > 0 a
+    each tick advances every live instance by up to `steps_per_tick` steps
+    (one smmo_batch_step on wg_per_cu workgroups per CU, 0 = all that fit, in
+    `mode`); finished instances leave and free their memory.  With tick_s > 0 a
     launch starts at most every tick_s seconds (a batching window: instances
     wait for the next tick, so each launch carries more of them, for fewer
     GPU-seconds and a longer time to completion); 0 launches back to back
@@ -197,7 +201,8 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
     seconds, busy seconds (GPU time of the launches), the mean number of live
     instances per step run, admission host times (ms, outside the latencies)
     and admission delays."""
-    fleet = Fleet(arena, max(1, min(max_instances, len(reqs))), lookups=lookups, block_objects=block_objects)
+    fleet = Fleet(arena, max(1, min(max_instances, len(reqs))), lookups=lookups, block_objects=block_objects,
+                  mode=mode)
     fleet.batch.set_grid(wg_per_cu)
     pending = deque(sorted(reqs, key=lambda r: r.arrival))
     lat, admit_delay, admit_ms, done_s, results = [], [], [], [], {}

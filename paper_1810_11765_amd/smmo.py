@@ -48,6 +48,7 @@ TUNE_STATS = 4
 TUNE_FORCE_FAIL = 8
 TUNE_FLAT_ENUM = 32
 TUNE_ROTATED_START = 64
+BATCH_PHASED, BATCH_PERSISTENT = 0, 1          # smmo_batch_set_mode
 COUNTERS = ["alloc_obj", "free_obj", "block_init", "block_free", "inval_rollback", "type_rollback",
             "find_fail", "reserve_fail", "spin", "reserve_atomic", "guard_alloc", "guard_spin", "guard_inval",
             "oom"]
@@ -459,6 +460,7 @@ def _bind_batch():
         "smmo_batch_add_wator": ([P, P, P, u32, P, P], i), "smmo_batch_remove": ([P, u32], i),
         "smmo_batch_step": ([P, u32, P], i), "smmo_batch_remaining": ([P, P, P], i),
         "smmo_batch_grid": ([P, P], i), "smmo_batch_set_grid": ([P, u32], i),
+        "smmo_batch_set_mode": ([P, u32], i),
         "smmo_batch_capture_graph": ([P, u32, u32, P, P], i), "smmo_batch_graph_launch": ([P, P], i),
         "smmo_batch_graph_destroy": ([P], i),
     }
@@ -553,6 +555,10 @@ class Batch:
         """Workgroups per CU of the persistent kernel (0 = all that fit)."""
         check(lib().smmo_batch_set_grid(self.h, wg_per_cu))
 
+    def set_mode(self, mode: int) -> None:
+        """BATCH_PHASED (one launch per phase, the default) or BATCH_PERSISTENT."""
+        check(lib().smmo_batch_set_mode(self.h, mode))
+
     def close(self):
         if getattr(self, "h", None):
             lib().smmo_batch_destroy(self.h)
@@ -560,7 +566,7 @@ class Batch:
 
 
 class BatchGraph:
-    """An instantiated HIP graph of persistent batch steps (smmo_batch_capture_graph)."""
+    """An instantiated HIP graph of batch steps (smmo_batch_capture_graph)."""
 
     def __init__(self, handle):
         self.h = handle

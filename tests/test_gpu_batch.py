@@ -1,6 +1,7 @@
 """GPU parity of the batched and served predator-prey forms: every instance's
 result is the oracle's for its own size and seed, alone or in the mix, with
-the persistent batch kernel, graph replay and continuous admission."""
+both batch forms (one launch per phase, one persistent kernel), graph replay
+and continuous admission."""
 import numpy as np
 import pytest
 
@@ -40,27 +41,29 @@ def _check(results, reqs, steps):
         assert np.array_equal(energy[kind == 2], oe[ok == 2]), f"request {r.rid}: energies differ"
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("per_launch,graph", [(1, False), (7, False), (1, True), (10, True)])
-def test_batched_instances_match_oracle(per_launch, graph):
-    say("batched", per_launch, graph)
+def test_batched_instances_match_oracle(per_launch, graph, mode):
+    say("batched", per_launch, graph, mode)
     sv = SV()
     reqs = sv.make_requests(seed=5, count=12, lo=12, hi=100)
     arena = S().Arena(sv.arena_bytes_for(reqs))
-    results, dt, _ = sv.run_batched(reqs, 40, arena, per_launch=per_launch, graph=graph)
+    results, dt, _ = sv.run_batched(reqs, 40, arena, per_launch=per_launch, graph=graph, mode=mode)
     _check(results, reqs, 40)
     free, largest = arena.stats()
     assert free == largest                                   # every range returned and merged
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("wg_per_cu", [1, 2])
-def test_batched_smaller_grid_matches_oracle(wg_per_cu):
-    """The persistent kernel on 1 or 2 workgroups per CU (the autotuner's
-    knob): same results."""
-    say("batched grid", wg_per_cu)
+def test_batched_smaller_grid_matches_oracle(wg_per_cu, mode):
+    """Both batch forms on 1 or 2 workgroups per CU (the autotuner's knob):
+    same results."""
+    say("batched grid", wg_per_cu, mode)
     sv = SV()
     reqs = sv.make_requests(seed=15, count=12, lo=12, hi=100)
     arena = S().Arena(sv.arena_bytes_for(reqs))
-    results, dt, grid = sv.run_batched(reqs, 40, arena, per_launch=3, graph=False, wg_per_cu=wg_per_cu)
+    results, dt, grid = sv.run_batched(reqs, 40, arena, per_launch=3, graph=False, wg_per_cu=wg_per_cu, mode=mode)
     assert grid == 256 * wg_per_cu or grid < 256 * wg_per_cu      # capped by residency
     _check(results, reqs, 40)
 
@@ -81,7 +84,7 @@ def test_batched_with_the_tuned_shape_matches_oracle():
     arena = S().Arena(sv.arena_bytes_for(reqs, bo))
     results, dt, grid = sv.run_batched(reqs, 50, arena, per_launch=shape["steps_per_launch"], graph=True,
                                        wg_per_cu=shape["wg_per_cu"], lookups=shape.get("lookups", 5),
-                                       block_objects=bo)
+                                       block_objects=bo, mode=shape.get("mode", 0))
     _check(results, reqs, 50)
 
 
@@ -172,8 +175,8 @@ def test_batched_three_level_bitmaps_match_oracle():
 
 def test_config_5_batched_and_served_against_oracle_goldens():
     """The configuration as stated: 256 instances of seed 42, side log-uniform
-    in [64, 1024), 200 steps each, batched (persistent kernel, graph replay,
-    the bench's launch shape) and served (Poisson arrivals at 50/s).  Every
+    in [64, 1024), 200 steps each, batched (graph replay, the bench's launch
+    shape, and the other batch form) and served (Poisson arrivals at 50/s).  Every
     instance's final state hashes to the value the oracle stored in
     tests/golden (written by tests/golden/make_goldens.py from oracle/ only)."""
     import os
@@ -187,7 +190,7 @@ def test_config_5_batched_and_served_against_oracle_goldens():
     assert sorted(golden) == [r.rid for r in reqs]
     for r in reqs:
         assert golden[r.rid][:2] == (r.side, r.seed)
-    shape = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5, "block_objects": 64}
+    shape = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5, "block_objects": 64, "mode": 0}
     path = os.path.join(os.path.dirname(sv.__file__), "tuned_launch.json")
     shape.update(tune.load(path, "predator-prey batched 256 instances 200 steps") or {})
     bo = shape["block_objects"]
@@ -204,16 +207,22 @@ def test_config_5_batched_and_served_against_oracle_goldens():
 
     say("config 5 batched", shape)
     results, dt, _ = sv.run_batched(reqs, 200, arena, per_launch=shape["steps_per_launch"], graph=True,
-                                    wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"], block_objects=bo)
+                                    wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"], block_objects=bo,
+                                    mode=shape["mode"])
     check(results, "batched")
+    other = 1 - shape["mode"]
+    say("config 5 batched, mode", other)
+    results, dt, _ = sv.run_batched(reqs, 200, arena, per_launch=10, graph=True, block_objects=bo, mode=other)
+    check(results, "batched, other form")
     say("config 5 served")
     out = sv.serve(reqs, 200, arena, time_scale=1.0, wg_per_cu=shape["wg_per_cu"], lookups=shape["lookups"],
-                   steps_per_tick=shape["steps_per_launch"], block_objects=bo)
+                   steps_per_tick=shape["steps_per_launch"], block_objects=bo, mode=shape["mode"])
     check(out["results"], "served")
 
 
-def test_captured_batch_graph_replayed_several_times_matches_oracle():
-    """smmo_batch_capture_graph: one launch of 5 steps captured once and
+@pytest.mark.parametrize("mode", [0, 1])
+def test_captured_batch_graph_replayed_several_times_matches_oracle(mode):
+    """smmo_batch_capture_graph: one launch group of 5 steps captured once and
     replayed six times, with eager work (state dumps) and synchronizations
     between the replays; after every replay each instance equals the oracle
     at 5, 10, ... 30 steps.  Once the instance set changes, the graph is
@@ -222,7 +231,7 @@ def test_captured_batch_graph_replayed_several_times_matches_oracle():
     S_ = S()
     reqs = sv.make_requests(seed=11, count=6, lo=16, hi=90)
     arena = S_.Arena(sv.arena_bytes_for(reqs))
-    fleet = sv.Fleet(arena, 8)
+    fleet = sv.Fleet(arena, 8, mode=mode)
     for r in reqs:
         assert fleet.admit(r, 30)
     stream = torch.cuda.Stream()
@@ -257,4 +266,6 @@ def test_batch_graph_capture_rejects_the_null_stream():
     out = C.c_void_p()
     rc = S_.lib().smmo_batch_capture_graph(b.h, 1, 1, None, C.byref(out))
     assert rc == -1 and not out.value
+    with pytest.raises(S_.SmmoError):
+        b.set_mode(2)
     b.close()
