@@ -65,7 +65,7 @@ def instance_state(w: WaTor):
 
 class Fleet:
     """A batch plus the instances it runs.  The host counts every instance's
-    remaining steps itself (the batch kernel advances each by min(steps,
+    remaining steps itself (the batch advances each by min(steps,
     remaining)), so finding finished instances needs no device readback; the
     device's own count is checked once, when an instance leaves."""
 

@@ -154,7 +154,7 @@ def test_serving_waits_for_memory():
 def test_batched_three_level_bitmaps_match_oracle():
     """Instances large enough for three-level block bitmaps (more than 4,096
     blocks: sides 400 and 512) next to small ones, batched (graph replay) and
-    served: the top-down and level-0-probe searches of the batch kernel
+    served: the top-down and level-0-probe searches of the batch kernels
     against the oracle."""
     sv = SV()
     from paper_1810_11765_amd import inputs
