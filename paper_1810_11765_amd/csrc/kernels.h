@@ -169,8 +169,18 @@ struct Obj {
 // there are at most 16,384 units.
 // kSnap: read the iteration words of k_snapshot (always so when the do-all
 // covers a class and its subclasses, whose methods may create objects of any
-// of them).
-template <class M, bool kSnap = M::kSnapshot>
+// of them).  kRecord (methods that create and destroy no object of any class,
+// RecordsSnapshot below): after the method ran on a block, its lane 0 stores
+// the block's live slots as its iteration word, so the class's snapshot is
+// taken in passing and the next do-all that needs one skips the k_snapshot
+// pass.
+template <class M>
+struct RecordsSnapshot {
+    template <class T> static constexpr bool test(decltype(T::kRecordSnapshot)*) { return T::kRecordSnapshot; }
+    template <class T> static constexpr bool test(...) { return false; }
+    static constexpr bool value = test<M>(nullptr);
+};
+template <class M, bool kSnap = M::kSnapshot, bool kRecord = false>
 __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls, uint32_t s_log2,
                                                           uint64_t nunits, const uint32_t* R,
                                                           const unsigned long long* nR, typename M::Args a) {
@@ -205,6 +215,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls
                 Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
                       wave_seed(wave, bid)};
                 M::run(o, prep, a);
+                if (kRecord && lane == 0) h.iter[bid] = live;
             }
         }
         return;
@@ -236,6 +247,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls
             Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
                   wave_seed(wave, bid)};
             M::run(o, prep, a);
+            if (kRecord && lane == 0) h.iter[bid] = live;
         }
     }
 }

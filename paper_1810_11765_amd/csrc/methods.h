@@ -346,6 +346,7 @@ __device__ inline void wator_nbrs(int32_t c, int32_t W, int32_t H, int32_t nb[4]
 struct MFishPlan {
     using Args = smmo_wator_args;
     static constexpr bool kSnapshot = false;
+    static constexpr bool kRecordSnapshot = true;     // creates and destroys nothing; the move phase needs one
     using Prep = WatorPrep;
     __device__ static Prep prepare(const DevHeap& h, uint32_t, const Args& a) { return wator_prep(h, a); }
     __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {
@@ -406,6 +407,7 @@ struct MFishMove {
 struct MSharkPlan {
     using Args = smmo_wator_args;
     static constexpr bool kSnapshot = false;
+    static constexpr bool kRecordSnapshot = true;     // creates and destroys nothing; the move phase needs one
     using Prep = WatorPrep;
     __device__ static Prep prepare(const DevHeap& h, uint32_t, const Args& a) { return wator_prep(h, a); }
     __device__ __forceinline__ static void run(const Obj& o, const Prep& p, const Args& a) {

@@ -45,8 +45,20 @@ struct smmo_heap {
     // the scratch list, resets it; a heap in a batch (changed by the batch
     // kernel behind the host's back) never caches.
     int32_t list_cls = -1;
+    // The class whose iteration words equal its allocation words, recorded
+    // in passing by the last do-all of a method that creates and destroys
+    // nothing (-1: none); reset with list_cls by every call that may change
+    // blocks.  A do-all that needs the class's snapshot then skips k_snapshot.
+    int32_t snap_cls = -1;
     bool in_batch = false;
 };
+
+// a call that may change blocks (or write the scratch list): the cached block
+// list and the recorded snapshot are no longer current
+inline void blocks_changed(smmo_heap* H) {
+    H->list_cls = -1;
+    H->snap_cls = -1;
+}
 
 // Static device scratch of smmo_parallel_do_static_scratch (see below):
 // counters (1 KiB), then up to kStaticListBlocks block ids.
@@ -363,15 +375,17 @@ uint32_t subtree(const smmo_heap* H, uint32_t cls, uint32_t* out) {
     return n;
 }
 
-// One do-all kernel on one class; with snap_here, the class's snapshot first.
-template <class M, bool kSnap>
+// One do-all kernel on one class; with snap_here, the class's snapshot first
+// (unless a do-all recorded it since the class's blocks last changed); with
+// kRecord, the kernel records it.
+template <class M, bool kSnap, bool kRecord = false>
 int launch_doall_one(smmo_heap* H, uint32_t cls, const typename M::Args& a, bool snap_here, hipStream_t s) {
     int rc = SMMO_OK;
     const bool list = build_block_list(H, cls, s, &rc);
     if (rc) return rc;
     const uint32_t* R = list ? scratch_R(H) : nullptr;
     const unsigned long long* nR = list ? scratch_counter(H, 3) : nullptr;
-    if (snap_here) {
+    if (snap_here && !(H->snap_cls == (int32_t)cls && !H->in_batch)) {
         if (list) k_snapshot<<<list_grid(H), 256, 0, s>>>(H->dev, cls, R, nR);
         else k_snapshot<<<grid_for(H->hdr.num_blocks, 256), 256, 0, s>>>(H->dev, cls, nullptr, nullptr);
         LAUNCH_CHECK("k_snapshot");
@@ -390,13 +404,14 @@ int launch_doall_one(smmo_heap* H, uint32_t cls, const typename M::Args& a, bool
     }
     if (H->armed_start || H->armed_stop) {
         // the kernel's own start and end, recorded by the dispatch itself
-        hipExtLaunchKernelGGL((k_doall<M, kSnap>), dim3(grid), dim3(kBlockThreads), 0, s, H->armed_start,
+        hipExtLaunchKernelGGL((k_doall<M, kSnap, kRecord>), dim3(grid), dim3(kBlockThreads), 0, s, H->armed_start,
                               H->armed_stop, 0, H->dev, cls, s_log2, nunits, R, nR, a);
         H->armed_start = H->armed_stop = nullptr;
     } else {
-        k_doall<M, kSnap><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, R, nR, a);
+        k_doall<M, kSnap, kRecord><<<grid, kBlockThreads, 0, s>>>(H->dev, cls, s_log2, nunits, R, nR, a);
     }
     LAUNCH_CHECK("k_doall");
+    if (kRecord) H->snap_cls = (int32_t)cls;
     return SMMO_OK;
 }
 
@@ -423,7 +438,7 @@ int launch_doall(smmo_heap* H, uint32_t cls, const void* args, uint64_t bytes, h
             if ((rc = launch_doall_one<M, true>(H, cl[i], a, false, s))) return rc;
         return SMMO_OK;
     }
-    if (n == 1) return launch_doall_one<M, M::kSnapshot>(H, cls, a, M::kSnapshot, s);
+    if (n == 1) return launch_doall_one<M, M::kSnapshot, RecordsSnapshot<M>::value>(H, cls, a, M::kSnapshot, s);
     // class and subclasses (Sec. 2.1): one kernel per class, every class's
     // iteration words taken before the first, so no kernel visits objects an
     // earlier one created
@@ -590,7 +605,7 @@ int smmo_heap_destroy(smmo_heap* heap) {
 
 int smmo_heap_reset(smmo_heap* heap, void* stream) {
     TimingScope timing(heap, false);
-    if (heap) heap->list_cls = -1;             // blocks (or the scratch list) change
+    if (heap) blocks_changed(heap);
     if (!heap) return fail(SMMO_EINVAL, "null heap");
     return init_device(heap, S(stream));
 }
@@ -644,7 +659,7 @@ int smmo_set_tuning(smmo_heap* heap, uint32_t flags, uint32_t lookups, uint32_t 
 int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_id, const void* args,
                       uint64_t args_bytes, void* stream) {
     TimingScope timing(heap, false);
-    if (heap) heap->list_cls = -1;             // blocks (or the scratch list) change
+    if (heap) blocks_changed(heap);
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     if (n == 0) return SMMO_OK;
@@ -659,7 +674,7 @@ int smmo_parallel_new(smmo_heap* heap, uint32_t cls, uint64_t n, uint32_t ctor_i
 int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32_t per_thread, uint32_t ctor_id,
                         const void* args, uint64_t args_bytes, void* stream) {
     TimingScope timing(heap, false);
-    if (heap) heap->list_cls = -1;             // blocks (or the scratch list) change
+    if (heap) blocks_changed(heap);
     int rc = check_heap_cls(heap, cls);
     if (rc) return rc;
     if (nthreads == 0 || per_thread == 0) return SMMO_OK;
@@ -677,7 +692,7 @@ int smmo_parallel_alloc(smmo_heap* heap, uint32_t cls, uint64_t nthreads, uint32
 int smmo_parallel_destroy(smmo_heap* heap, const uint64_t* refs, uint64_t nthreads, uint32_t per_thread,
                           void* stream) {
     TimingScope timing(heap, false);
-    if (heap) heap->list_cls = -1;             // blocks (or the scratch list) change
+    if (heap) blocks_changed(heap);
     if (!heap) return fail(SMMO_EINVAL, "null heap");
     if (nthreads == 0 || per_thread == 0) return SMMO_OK;
     if (!refs) return fail(SMMO_EINVAL, "null refs");
@@ -798,7 +813,7 @@ static int parallel_do(smmo_heap* heap, uint32_t cls, uint32_t method_id, const 
 static int parallel_do_call(smmo_heap* heap, uint32_t cls, uint32_t method_id, const void* args,
                             uint64_t args_bytes, void* stream, bool from_snapshot) {
     const int rc = parallel_do(heap, cls, method_id, args, args_bytes, stream, from_snapshot);
-    if (heap && !method_keeps_blocks(method_id)) heap->list_cls = -1;
+    if (heap && !method_keeps_blocks(method_id)) blocks_changed(heap);
     return rc;
 }
 
@@ -1293,8 +1308,8 @@ int smmo_batch_add_wator(smmo_batch* B, smmo_heap* heap, const smmo_wator_args* 
     HIP_TRY(hipMemcpyAsync(&B->d_desc[slot], &d, sizeof d, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(&B->d_prog[slot], &pr, sizeof pr, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
-    heap->in_batch = true;                      // the batch kernel changes its blocks from now on
-    heap->list_cls = -1;
+    heap->in_batch = true;                      // the batch kernels change its blocks from now on
+    blocks_changed(heap);
     B->used[slot] = 1;
     B->weight[slot] = (uint64_t)args->width * (uint64_t)args->height;
     // one wave per block of the instance's heap at most (units of one block)

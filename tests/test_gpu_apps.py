@@ -170,6 +170,37 @@ def test_wator_ragged_parity(Wd, Hd, blocks, seed):
     _wator_check(w, 120, core.c3_run(w.kind0, Wd, Hd, seed, 120))
 
 
+@pytest.mark.parametrize("blocks", [256, 300000])
+def test_plan_phase_records_the_snapshot_of_its_class(blocks):
+    """A plan do-all (creates and destroys nothing) records its class's
+    snapshot in passing: right after it, every allocated fish block's
+    iteration word equals its live slots, in a flat-scanned and in a
+    block-listed heap; the step then continues (the move phase uses it) and
+    30 steps still equal the oracle."""
+    from oracle import heapcheck
+    from paper_1810_11765_amd import smmo as S
+    say("recorded snapshot", blocks)
+    w = W().WaTor(seed=9, width=97, height=61, num_blocks=blocks)
+    w.populate()
+    for _ in range(3):
+        w.step()
+    w.t += 1
+    w.args.step = w.t
+    w.heap.parallel_do(w.FISH, S.M_WATOR_FISH_PLAN, w.args)
+    raw = heapcheck.RawHeap(w.heap.dump_raw())
+    fish = raw.bits(1 + w.FISH)
+    pad = np.uint64((0xFFFFFFFFFFFFFFFF << raw.capacity[w.FISH]) & 0xFFFFFFFFFFFFFFFF) \
+        if raw.capacity[w.FISH] < 64 else np.uint64(0)
+    assert fish.any()
+    assert np.array_equal(raw.iter[fish], raw.alloc[fish] & ~pad)
+    w.heap.parallel_do(w.FISH, S.M_WATOR_FISH_MOVE, w.args)
+    w.heap.parallel_do(w.SHARK, S.M_WATOR_SHARK_PLAN, w.args)
+    w.heap.parallel_do(w.SHARK, S.M_WATOR_SHARK_MOVE, w.args)
+    for _ in range(26):
+        w.step()
+    _wator_check(w, 30, core.c3_run(w.kind0, 97, 61, 9, 30))
+
+
 @pytest.mark.parametrize("bo,blocks", [(32, 65536), (16, 131072)])
 def test_wator_parity_with_fewer_objects_per_block(bo, blocks):
     """The layout knob: bo objects per block of the smallest class (fish
