@@ -40,7 +40,7 @@ def kernel_source_hash() -> str:
 
 
 def short_name(kernel: str, grid: int) -> str:
-    """``smmo::k_doall<smmo::MLifeCommit, false>`` or ``void
+    """``smmo::k_doall<smmo::MLifeCommit, false, false>`` or ``void
     k_doall<MLifeCommit>(DevHeap, ...)`` -> ``k_doall<MLifeCommit>`` (the
     profiler prints either form); the streaming sweep at the bench's
     2^21-block shape gets ``@2^21``."""
@@ -53,7 +53,7 @@ def short_name(kernel: str, grid: int) -> str:
         if c == "(" and depth == 0 and i > 0:
             k = k[:i]
             break
-    k = re.sub(r", (true|false)>", ">", k)
+    k = re.sub(r"(, (true|false))+>", ">", k)
     if k.startswith("k_doall_axpy<") and grid == SWEEP_GRID:
         k += "@2^21"
     return k

@@ -39,6 +39,7 @@ def test_scaled_bytes_per_launch(tmp_path):
     assert k["k_doall_axpy<4>"]["bytes_per_launch"] == (2 * 10 + 5) * 1024
     assert not any(n.startswith("__amd") for n in k)
     assert counters.short_name("smmo::k_doall<smmo::MLifeCommit, false>", 786432) == "k_doall<MLifeCommit>"
+    assert counters.short_name("smmo::k_doall<smmo::MFishPlan, false, true>", 1) == "k_doall<MFishPlan>"
     assert counters.short_name("k_destroy(DevHeap, unsigned long const*)", 1) == "k_destroy"
     assert rec["source_sha256"] == counters.kernel_source_hash()
     counters.main(["x", str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "o.json")])
