@@ -725,7 +725,7 @@ def autotune_suite(torch, workloads, cache):
     def same_states(a, b):
         return all(all(np.array_equal(x, y) for x, y in zip(a[k][0], b[k][0])) and a[k][1] == b[k][1] == 0
                    for k in a)
-    rec = tune.search(batched, {"mode": [S.BATCH_PHASED, S.BATCH_PERSISTENT], "wg_per_cu": [0, 1, 2, 3],
+    rec = tune.search(batched, {"mode": [S.BATCH_PHASED, S.BATCH_PERSISTENT], "wg_per_cu": [0, 8, 24, 32, 2],
                                 "steps_per_launch": [1, 2, 5, 10], "lookups": [5, 3, 8, 12],
                                 "block_objects": [64, 32]}, reps=2, equal=same_states)
     tune.save(cache, "predator-prey batched 256 instances 200 steps", rec)

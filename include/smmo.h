@@ -561,12 +561,13 @@ int smmo_batch_graph_destroy(smmo_batch_graph* graph);
 /* Remaining steps of every slot (0xFFFFFFFF for an empty slot), to host
  * memory of max_instances entries.  Synchronizes. */
 int smmo_batch_remaining(smmo_batch* batch, uint32_t* out, void* stream);
-/* Workgroups of the batch's launches (the occupancy-bounded grid of the
- * current mode). */
+/* Workgroups of the batch's launches (the grid of the current mode). */
 int smmo_batch_grid(const smmo_batch* batch, uint32_t* workgroups);
-/* Use wg_per_cu workgroups per CU (0: as many as can be resident, the
- * default); more than can be resident is capped.  The schedule is rebuilt at
- * the next step.  Results do not depend on it. */
+/* Use wg_per_cu workgroups per CU.  0 selects the mode's default: 16 for the
+ * phased form (its kernels need no co-residency, so the grid may exceed what
+ * is resident at once; at most 32), every workgroup that can be resident for
+ * the persistent kernel (which is also its most).  Larger values are capped.
+ * The schedule is rebuilt at the next step.  Results do not depend on it. */
 int smmo_batch_set_grid(smmo_batch* batch, uint32_t wg_per_cu);
 /* SMMO_BATCH_PHASED or SMMO_BATCH_PERSISTENT (SMMO_EINVAL otherwise); the
  * grid follows the mode's occupancy and the schedule is rebuilt at the next

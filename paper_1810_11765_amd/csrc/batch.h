@@ -171,7 +171,11 @@ __global__ __launch_bounds__(256) void k_batch_wator(BatchDesc* desc, BatchProg*
 // needed, and each phase's kernel holds only its own method (fewer registers,
 // more waves per SIMD than the persistent kernel, which holds all four).
 template <class M, bool kShark, bool kSnap>
-__global__ __launch_bounds__(256) void k_batch_phase(const BatchDesc* __restrict__ desc,
+__global__ __launch_bounds__(256)
+#ifdef SMMO_PHASED_WPE
+__attribute__((amdgpu_waves_per_eu(SMMO_PHASED_WPE)))
+#endif
+void k_batch_phase(const BatchDesc* __restrict__ desc,
                                                       const BatchProg* __restrict__ prog,
                                                       const BatchSched* __restrict__ sched,
                                                       const int32_t* __restrict__ wg_inst, uint32_t s) {

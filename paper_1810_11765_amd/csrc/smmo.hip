@@ -1111,11 +1111,12 @@ struct smmo_batch {
     smmo_arena* arena;
     uint32_t max_inst;
     uint32_t grid;                              // persistent workgroups in use
-    uint32_t grid_max;                          // all that can be resident (tables sized for it)
-    uint32_t cus, per_cu;                       // compute units, resident workgroups per CU (current mode)
-    uint32_t per_cu_mode[2];                    // resident workgroups per CU of each mode's kernels
+    uint32_t grid_max;                          // the largest grid of either mode (tables sized for it)
+    uint32_t grid_bar;                          // the persistent kernel's largest grid (barrier words sized for it)
+    uint32_t cus, per_cu;                       // compute units, workgroups per CU of the current grid
+    uint32_t per_cu_mode[2];                    // most workgroups per CU of each mode
     uint32_t mode;                              // SMMO_BATCH_PHASED or SMMO_BATCH_PERSISTENT
-    uint32_t wg_req = 0;                        // requested workgroups per CU (0: all resident)
+    uint32_t wg_req = 0;                        // requested workgroups per CU (0: the mode's default)
     uint8_t* dev;                               // device tables (from the arena)
     BatchDesc* d_desc;
     BatchProg* d_prog;
@@ -1209,6 +1210,13 @@ int smmo_arena_stats(const smmo_arena* A, uint64_t* free_bytes, uint64_t* larges
 }
 
 // ------------------------------------------------------------- batch ----
+// workgroups per CU of the phase kernels: at most, and by default
+constexpr uint32_t kPhasedMaxPerCu = 32, kPhasedDefaultPerCu = 16;
+
+static uint32_t default_per_cu(const smmo_batch* B) {
+    return B->mode == SMMO_BATCH_PHASED ? kPhasedDefaultPerCu : B->per_cu_mode[SMMO_BATCH_PERSISTENT];
+}
+
 int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
     if (!arena || !out || max_inst == 0 || max_inst > 65536) return fail(SMMO_EINVAL, "batch: bad arguments");
     int dev = 0, cus = 0, per_cu = 0;
@@ -1225,22 +1233,27 @@ int smmo_batch_create(smmo_arena* arena, uint32_t max_inst, smmo_batch** out) {
     }
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_wator, 256, 0));
     if (per_cu < 1 || per_cu_phased < 1) return fail(SMMO_EHIP, "batch kernels cannot be resident");
+    if (per_cu > (int)kPhasedMaxPerCu) per_cu = (int)kPhasedMaxPerCu;
     smmo_batch* B = new smmo_batch();
     B->arena = arena;
     B->max_inst = max_inst;
     // the persistent kernel needs every workgroup resident at once for the
-    // instance barriers: each mode's grid is the occupancy the runtime reports
-    // for its kernels; the tables are sized for the larger
+    // instance barriers: its grid is the occupancy the runtime reports.  The
+    // phase kernels need no co-residency, so their grid may exceed it: more
+    // workgroups give every instance more waves and keep the CUs busy while
+    // others finish (config 5: 401 ms at the 5 resident per CU, 333 at 16, 326
+    // at 32); the tables are sized for the larger grid
     B->cus = (uint32_t)cus;
-    B->per_cu_mode[SMMO_BATCH_PHASED] = (uint32_t)per_cu_phased;
+    B->per_cu_mode[SMMO_BATCH_PHASED] = kPhasedMaxPerCu;
     B->per_cu_mode[SMMO_BATCH_PERSISTENT] = (uint32_t)per_cu;
     B->mode = SMMO_BATCH_PHASED;
-    B->per_cu = B->per_cu_mode[B->mode];
+    B->per_cu = default_per_cu(B);
     B->grid = (uint32_t)cus * B->per_cu;
-    B->grid_max = (uint32_t)cus * (uint32_t)std::max(per_cu, per_cu_phased);
+    B->grid_max = (uint32_t)cus * std::max((uint32_t)per_cu, kPhasedMaxPerCu);
+    B->grid_bar = (uint32_t)cus * (uint32_t)per_cu;
     const uint64_t bytes = align_up(sizeof(BatchDesc) * max_inst, 256) + align_up(sizeof(BatchProg) * max_inst, 256) +
                            align_up(sizeof(BatchSched) * max_inst, 256) + align_up(4ull * B->grid_max, 256) +
-                           align_up(4ull * max_inst * bar_words(B->grid_max), 256);
+                           align_up(4ull * max_inst * bar_words(B->grid_bar), 256);
     void* p = nullptr;
     int rc = smmo_arena_alloc(arena, bytes, &p);
     if (rc) { delete B; return rc; }
@@ -1390,7 +1403,7 @@ static int batch_launch(smmo_batch* B, uint32_t steps, hipStream_t s) {
     }
     // one persistent launch: the instance barrier counters are cleared by a
     // kernel (not a memset, so the pair can be captured and replayed)
-    const uint32_t stride = bar_words(B->grid_max);
+    const uint32_t stride = bar_words(B->grid_bar);
     const uint64_t bar_u64 = ((uint64_t)B->max_inst * stride + 1) / 2;
     k_fill_u64<<<grid_for(bar_u64, 256), 256, 0, s>>>(reinterpret_cast<unsigned long long*>(B->d_bar), bar_u64, 0);
     LAUNCH_CHECK("k_fill_u64");
@@ -1474,7 +1487,9 @@ int smmo_batch_grid(const smmo_batch* B, uint32_t* workgroups) {
 int smmo_batch_set_grid(smmo_batch* B, uint32_t wg_per_cu) {
     if (!B) return fail(SMMO_EINVAL, "null batch");
     B->wg_req = wg_per_cu;
-    const uint32_t w = wg_per_cu == 0 || wg_per_cu > B->per_cu ? B->per_cu : wg_per_cu;
+    const uint32_t most = B->per_cu_mode[B->mode];
+    const uint32_t w = wg_per_cu == 0 ? default_per_cu(B) : (wg_per_cu > most ? most : wg_per_cu);
+    B->per_cu = w;
     B->grid = B->cus * w;
     B->dirty = true;
     ++B->generation;
@@ -1485,7 +1500,6 @@ int smmo_batch_set_mode(smmo_batch* B, uint32_t mode) {
     if (!B) return fail(SMMO_EINVAL, "null batch");
     if (mode != SMMO_BATCH_PHASED && mode != SMMO_BATCH_PERSISTENT) return fail(SMMO_EINVAL, "batch: unknown mode %u", mode);
     B->mode = mode;
-    B->per_cu = B->per_cu_mode[mode];
     return smmo_batch_set_grid(B, B->wg_req);
 }
 

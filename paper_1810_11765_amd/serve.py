@@ -188,8 +188,8 @@ def serve(reqs, steps: int, arena: S.Arena, time_scale: float = 1.0, max_instanc
     """Continuous batching over arrivals (arrival times scaled by time_scale):
     between launches, arrived requests are admitted while the arena has room;
     each tick advances every live instance by up to `steps_per_tick` steps
-    (one smmo_batch_step on wg_per_cu workgroups per CU, 0 = all that fit, in
-    `mode`); finished instances leave and free their memory.  With tick_s > 0 a
+    (one smmo_batch_step on wg_per_cu workgroups per CU, 0 = the form's default,
+    in `mode`); finished instances leave and free their memory.  With tick_s > 0 a
     launch starts at most every tick_s seconds (a batching window: instances
     wait for the next tick, so each launch carries more of them, for fewer
     GPU-seconds and a longer time to completion); 0 launches back to back

@@ -552,7 +552,7 @@ class Batch:
         return g.value
 
     def set_grid(self, wg_per_cu: int = 0) -> None:
-        """Workgroups per CU of the batch's launches (0 = all that fit)."""
+        """Workgroups per CU of the batch's launches (0 = the mode's default)."""
         check(lib().smmo_batch_set_grid(self.h, wg_per_cu))
 
     def set_mode(self, mode: int) -> None:
