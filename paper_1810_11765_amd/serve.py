@@ -148,8 +148,8 @@ def run_plain(reqs, steps: int, arena: S.Arena, block_objects: int = 64):
 def run_batched(reqs, steps: int, arena: S.Arena, per_launch: int = 1, graph: bool = False, wg_per_cu: int = 0,
                 lookups: int = 5, block_objects: int = 64, mode: int = S.BATCH_PHASED):
     """All instances admitted, then `steps` steps of the batch (`per_launch`
-    steps per smmo_batch_step call, wg_per_cu workgroups per CU, 0 = all that
-    fit; `lookups` active-block lookups per allocation; `mode` phased or
+    steps per smmo_batch_step call, wg_per_cu workgroups per CU, 0 = the batch
+    form's default; `lookups` active-block lookups per allocation; `mode` phased or
     persistent).  Returns (results, seconds of the stepping, grid
     workgroups)."""
     fleet = Fleet(arena, max(len(reqs), 1), lookups=lookups, block_objects=block_objects, mode=mode)
