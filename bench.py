@@ -30,6 +30,7 @@ METRIC = "alloc+destroy Mobj/s; parallel_do GB/s (% HBM peak); app steps/s plain
 TUNED_LAUNCH = os.path.join(ROOT, "paper_1810_11765_amd", "tuned_launch.json")
 HBM_PEAK_GBS = 8000.0
 CLOCK_HZ = 2.4e9                  # MI355X peak engine clock
+SERVE_STEPS_PER_TICK = 10         # steps per launch while serving (an instance's 200 steps in 20 ticks)
 SIMDS = 256 * 4                   # compute units x SIMDs per unit
 HOLD_CYCLES = 1 << 28           # spin-kernel length that holds the stream while launches are queued
 
@@ -482,16 +483,16 @@ def batch_sub(torch, steps=200, count=256):
     other, t_other, grid_other = sv.run_batched(reqs, steps, arena, per_launch=10, graph=True, mode=other_mode,
                                                 block_objects=tuned["block_objects"])
     served = sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"],
-                      steps_per_tick=tuned["steps_per_launch"], block_objects=tuned["block_objects"],
+                      steps_per_tick=SERVE_STEPS_PER_TICK, block_objects=tuned["block_objects"],
                       mode=tuned["mode"])
     # the same requests arriving 10x and 100x faster: more instances live at
     # once, so each launch has more work for the same step latency
     faster = {ts: sv.serve(reqs, steps, arena, time_scale=ts, wg_per_cu=tuned["wg_per_cu"],
-                           lookups=tuned["lookups"], steps_per_tick=tuned["steps_per_launch"],
+                           lookups=tuned["lookups"], steps_per_tick=SERVE_STEPS_PER_TICK,
                            block_objects=tuned["block_objects"], mode=tuned["mode"]) for ts in (0.1, 0.01)}
     # config 5's arrivals again, with batching windows of 20 and 50 ms between launches
     windowed = {w: sv.serve(reqs, steps, arena, time_scale=1.0, wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"],
-                            steps_per_tick=tuned["steps_per_launch"], block_objects=tuned["block_objects"], tick_s=w,
+                            steps_per_tick=SERVE_STEPS_PER_TICK, block_objects=tuned["block_objects"], tick_s=w,
                             mode=tuned["mode"])
                 for w in (0.02, 0.05)}
     runs = ([batched, base, other, served["results"]] + [f["results"] for f in windowed.values()] +
@@ -518,7 +519,7 @@ def batch_sub(torch, steps=200, count=256):
             "served_p50_step_ms": round(float(np.percentile(lat, 50)), 4),
             "served_p99_step_ms": round(float(np.percentile(lat, 99)), 4),
             "served_max_admit_delay_s": round(float(served["admit_delay_s"].max()), 4),
-            "served_steps_per_launch": tuned["steps_per_launch"],
+            "served_steps_per_launch": SERVE_STEPS_PER_TICK,
             "served_busy_over_batched": round(served["busy_s"] / t_batch, 2),
             "served_admission_ms_p50_p99": [round(float(np.percentile(served["admit_ms"], q)), 3) for q in (50, 99)],
             "served_mean_live_instances": round(served["mean_live"], 1),
