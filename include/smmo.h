@@ -84,14 +84,18 @@ typedef struct smmo_heap smmo_heap;          /* opaque host handle */
  *   bitmaps   uint64 words; bitmap b (0 = free, 1+T = allocated[T],
  *             1+ncls+T = active[T], Sec. 3.4) starts at word b*bitmap_words;
  *             its level l (0 = containers of block bits) starts
- *             level_off[l] words further and has level_words[l] words.
+ *             level_off[l] words further and has level_words[l] words,
+ *             word k of the level at level_off[l] + k*bitmap_stride (16:
+ *             every word on a 128-B line of its own, so that the atomics of
+ *             different words never queue on one line; the words between
+ *             are unused and zero).
  *             Bit i of level l+1 is the OR of word i of level l (Sec. 4.1.1).
  *   data      block b's data segment is at off_data + b*block_bytes.
  */
 #define SMMO_MAGIC 0x504145484F4D4D53ull /* "SMMOHEAP" in little-endian bytes */
 typedef struct smmo_raw_header {
     uint64_t magic;
-    uint64_t version;                        /* 1 */
+    uint64_t version;                        /* 2 */
     uint64_t num_blocks;                     /* M */
     uint64_t ncls;
     uint64_t block_bytes;
@@ -115,7 +119,7 @@ typedef struct smmo_raw_header {
     uint32_t tune_flags;                     /* SMMO_TUNE_* */
     uint32_t lookups;                        /* active-block lookup attempts r (Sec. 4.2) */
     uint32_t force_fail_ppm;                 /* fault injection rate of try_find_set */
-    uint32_t reserved0;
+    uint32_t bitmap_stride;                  /* words between consecutive words of a bitmap level */
     uint32_t superclass[SMMO_MAX_CLASSES];   /* as in smmo_class_desc (0: none) */
 } smmo_raw_header;
 

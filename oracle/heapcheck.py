@@ -9,7 +9,8 @@ kernel"):
 
   H1 container consistency of every level of every block bitmap
      (Sec. 4.1.1 and App. A.5, Definition "Consistency")
-  H2 no bit beyond the bitmap's size is set
+  H2 no bit beyond the bitmap's size is set, and the unused words between
+     the words of a level (the layout's word stride) are zero
   H3 every block is either free or allocated to exactly one class
      (Sec. 3.4: free bitmap, one allocation bitmap per class)
   H4 a free block's allocation word is all ones (Alg. 9, invalidated; a
@@ -61,6 +62,10 @@ class RawHeap:
         self.field_bytes = fb.reshape(MAX_CLASSES, MAX_FIELDS)[: self.ncls]
         self.field_off = fo.reshape(MAX_CLASSES, MAX_FIELDS)[: self.ncls]
         self.tune_flags, self.lookups, self.force_fail_ppm = struct.unpack_from("<III", b, 2528)
+        # format 2 spaces the words of a level `bitmap_stride` words apart
+        self.stride = struct.unpack_from("<I", b, 2540)[0] if self.version >= 2 else 1
+        if self.stride < 1:
+            raise ValueError("bitmap word stride 0")
         # 1 + superclass id per class (0: none)
         self.superclass = list(struct.unpack_from("<16I", b, 2544))[: self.ncls]
         M = self.M
@@ -75,7 +80,13 @@ class RawHeap:
     # bitmap b: 0 free, 1+T allocated[T], 1+ncls+T active[T]
     def level(self, b: int, l: int) -> np.ndarray:
         base = b * self.bitmap_words + self.level_off[l]
-        return self.bm[base: base + self.level_words[l]]
+        return np.ascontiguousarray(self.bm[base: base + self.level_words[l] * self.stride: self.stride])
+
+    def level_gaps(self, b: int, l: int) -> np.ndarray:
+        """The unused words between the words of level l of bitmap b."""
+        base = b * self.bitmap_words + self.level_off[l]
+        span = self.bm[base: base + self.level_words[l] * self.stride].reshape(-1, self.stride)
+        return span[:, 1:].ravel()
 
     def bits(self, b: int) -> np.ndarray:
         """Level-0 bits of bitmap b as a bool array of length M."""
@@ -105,6 +116,8 @@ def check(raw: RawHeap) -> dict:
             assert len(w) == (nbits + 63) // 64, (b, l, len(w), nbits)
             bits = np.unpackbits(w.view(np.uint8), bitorder="little").astype(bool)
             assert not bits[nbits:].any(), f"bitmap {b} level {l}: bits beyond size {nbits} set"
+            gaps = np.nonzero(raw.level_gaps(b, l))[0]
+            assert len(gaps) == 0, f"bitmap {b} level {l}: unused words between its words are set {gaps[:8]}"
             if l + 1 < raw.nlevels:
                 up = raw.level(b, l + 1)
                 upbits = np.unpackbits(up.view(np.uint8), bitorder="little").astype(bool)[: len(w)]

@@ -116,9 +116,9 @@ __device__ inline void batch_phase(const DevHeap& h, uint32_t cls, const smmo_wa
         uint64_t my_word = 0, word;
         if (!M::kSnapshot) {       // no block of the class appears during a plan phase
             if (mine) my_word = at_load(&h.alloc[my_blk]);
-            word = at_load(l0 + w) & (unit_mask << first);
+            word = at_load(l0 + w * kBmStride) & (unit_mask << first);
         } else {
-            word = at_load(l0 + w) & (unit_mask << first);
+            word = at_load(l0 + w * kBmStride) & (unit_mask << first);
             if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
         }
         while (word) {

@@ -25,7 +25,7 @@ namespace smmo {
 constexpr uint32_t kSpinLimit = 1u << 18;
 
 __device__ inline uint64_t* bm_word(const DevHeap& h, uint32_t b, uint32_t level, uint64_t idx) {
-    return h.bm + (uint64_t)b * h.bitmap_words + h.level_off[level] + idx;
+    return h.bm + (uint64_t)b * h.bitmap_words + h.level_off[level] + idx * kBmStride;
 }
 
 // set(pos) from `level` upwards: switch the bit 0 -> 1, retrying while it is

@@ -19,6 +19,16 @@ constexpr uint64_t kOnes = ~0ull;
 constexpr uint64_t kFail = ~0ull;
 constexpr uint32_t kNoType = 0xFFFFFFFFu;
 constexpr uint32_t kWave = 64;
+// Bitmap word k of a level sits kBmStride words after word k-1: one word per
+// 128-B line.  Agent-scope atomics are performed past the L2 and queue per
+// line, and the few words of a level-0 active bitmap take every lookup and
+// every full/non-full transition of their class; on their own lines they
+// no longer wait on each other's atomics.  (-DSMMO_BM_STRIDE=1 builds the
+// dense layout for comparison.)
+#ifndef SMMO_BM_STRIDE
+#define SMMO_BM_STRIDE 16
+#endif
+constexpr uint64_t kBmStride = SMMO_BM_STRIDE;
 
 // Everything a kernel needs to address the heap; passed by value.
 struct DevHeap {

@@ -37,8 +37,9 @@ __global__ void k_init_bitmaps(DevHeap h, uint64_t nwords_total) {
         uint64_t nbits = h.M;
 #pragma unroll
         for (uint32_t l = 0; l < SMMO_MAX_LEVELS; ++l) {
-            if (l < h.nlevels && off >= h.level_off[l] && off < h.level_off[l] + h.level_words[l]) {
-                uint64_t k = off - h.level_off[l];
+            if (l < h.nlevels && off >= h.level_off[l] && off < h.level_off[l] + h.level_words[l] * kBmStride &&
+                (off - h.level_off[l]) % kBmStride == 0) {
+                uint64_t k = (off - h.level_off[l]) / kBmStride;
                 uint64_t lo = k * 64;
                 v = nbits >= lo + 64 ? kOnes : (nbits > lo ? ((1ull << (nbits - lo)) - 1) : 0);
             }
@@ -232,11 +233,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls
             // with the bitmap word; words of blocks whose bit is clear are
             // never used.
             if (mine) my_word = h.alloc[my_blk];
-            word = l0[w] & (span_mask << first);
+            word = l0[w * kBmStride] & (span_mask << first);
         } else {
             // Blocks may be (re)initialized meanwhile: read the bitmap word
             // first, then the iteration words of its set bits.
-            word = at_load(l0 + w) & (span_mask << first);
+            word = at_load(l0 + w * kBmStride) & (span_mask << first);
             if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
         }
         while (word) {
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(1024) void k_enum(DevHeap h, uint32_t bmid, uint64_
     const uint64_t lo = (uint64_t)t * per, hi = lo + per < W0 ? lo + per : W0;
     const uint64_t* l0 = bm_word(h, bmid, 0, 0);
     unsigned long long cnt = 0;
-    for (uint64_t i = lo; i < hi; ++i) cnt += popc64(l0[i]);
+    for (uint64_t i = lo; i < hi; ++i) cnt += popc64(l0[i * kBmStride]);
     // inclusive scan inside the wave
     unsigned long long inc = cnt;
 #pragma unroll
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(1024) void k_enum(DevHeap h, uint32_t bmid, uint64_
     __syncthreads();
     unsigned long long off = wsum[wv] + inc - cnt;
     for (uint64_t i = lo; i < hi && off < nb; ++i) {
-        uint64_t w = l0[i];
+        uint64_t w = l0[i * kBmStride];
         while (w && off < nb) {
             R[off++] = (uint32_t)((i << 6) | ctz64(w));
             w &= w - 1;

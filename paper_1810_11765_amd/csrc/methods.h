@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall_axpy(DevHeap h, uint32_
     const uint32_t ox = h.hdr->field_off[cls][a.fx], oy = h.hdr->field_off[cls][a.fy];
     const bool in_cap = 4 * q < N;
     for (uint64_t w = wave; w < nwords; w += nwaves) {
-        const uint64_t word = l0[w];
+        const uint64_t word = l0[w * kBmStride];
         if (!word) continue;
         // allocation word of block w*64 + lane
         const uint64_t my_alloc = ((word >> lane) & 1) ? h.alloc[(w << 6) | lane] : 0;

@@ -163,7 +163,8 @@ int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_r
         block = std::max(block, off);
     }
     hdr->magic = SMMO_MAGIC;
-    hdr->version = 1;
+    hdr->version = 2;
+    hdr->bitmap_stride = (uint32_t)kBmStride;
     hdr->num_blocks = M;
     hdr->ncls = ncls;
     hdr->block_bytes = block;
@@ -176,7 +177,7 @@ int compute_layout(const smmo_class_desc* cls, uint32_t ncls, uint64_t M, smmo_r
         uint64_t words = (nbits + 63) / 64;
         hdr->level_words[l] = words;
         hdr->level_off[l] = off;
-        off += align_up(words, 8);
+        off += align_up(words, 8) * kBmStride;
         ++l;
         if (words == 1) break;
         nbits = words;
@@ -971,7 +972,7 @@ static void dump_range(const smmo_raw_header& h, uint32_t cls, const uint64_t* l
     const uint64_t N = h.capacity[cls];
     const uint64_t valid = N >= 64 ? ~0ull : ((1ull << N) - 1);
     for (uint64_t b = first; b <= last; ++b) {
-        if (!((l0[b >> 6] >> (b & 63)) & 1)) continue;
+        if (!((l0[(b >> 6) * kBmStride] >> (b & 63)) & 1)) continue;
         uint64_t w = alloc[b - first] & valid;
         const uint8_t* blk = data + (b - first) * h.block_bytes;
         while (w) {
@@ -1015,12 +1016,12 @@ static int dump_walk(smmo_heap* heap, uint32_t cls, void* const* bufs, uint64_t*
     }
     // big heap: level 0 of allocated[cls], then only the runs of blocks it
     // names (close runs merged), so the copy is the class's size, not the heap's
-    std::vector<uint64_t> l0(W0);
-    HIP_TRY(hipMemcpyAsync(l0.data(), heap->base + l0_off, 8 * W0, hipMemcpyDeviceToHost, s));
+    std::vector<uint64_t> l0(W0 * kBmStride);
+    HIP_TRY(hipMemcpyAsync(l0.data(), heap->base + l0_off, 8 * W0 * kBmStride, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::vector<std::pair<uint64_t, uint64_t>> runs;       // [first, last] block
     for (uint64_t i = 0; i < W0; ++i)
-        for (uint64_t w = l0[i]; w; w &= w - 1) {
+        for (uint64_t w = l0[i * kBmStride]; w; w &= w - 1) {
             const uint64_t b = (i << 6) | (uint64_t)__builtin_ctzll(w);
             if (!runs.empty() && b <= runs.back().second + 8) runs.back().second = b;
             else runs.push_back({b, b});

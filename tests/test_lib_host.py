@@ -122,11 +122,11 @@ def test_heap_bytes_and_header_struct_offsets(tmp_path):
                 "int main(){P(magic)P(num_blocks)P(ncls)P(block_bytes)P(nlevels)P(level_words)P(level_off)"
                 "P(bitmap_words)P(off_status)P(off_type)P(off_alloc)P(off_iter)P(off_bitmaps)P(off_scratch)"
                 "P(scratch_bytes)P(off_data)P(total_bytes)P(capacity)P(nfields)P(field_bytes)P(field_off)"
-                "P(tune_flags)P(lookups)P(force_fail_ppm)P(superclass)return 0;}\n")
+                "P(tune_flags)P(lookups)P(force_fail_ppm)P(bitmap_stride)P(superclass)return 0;}\n")
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", prog], check=True)
     got = [int(v) for v in subprocess.run([prog], capture_output=True, text=True).stdout.split()]
     assert got == [0, 16, 24, 32, 40, 48, 96, 144, 152, 160, 168, 176, 184, 192, 200, 208, 216, 224, 352, 480,
-                   1504, 2528, 2532, 2536, 2544]
+                   1504, 2528, 2532, 2536, 2540, 2544]
     assert heapcheck.MAGIC == 0x504145484F4D4D53
 
 

@@ -8,7 +8,8 @@ pass; each dump below corrupts exactly one invariant and must be rejected
 with that invariant's message, so that none of the checks is vacuous:
 
   H1 container consistency of the levels (Sec. 4.1.1; App. A.5)
-  H2 no bit beyond the bitmap's size
+  H2 no bit beyond the bitmap's size; the unused words between the words of
+     a level (the layout's word stride) are zero
   H3 a block is free or allocated to exactly one class (Sec. 3.4)
   H4 a free block's allocation word is all ones (Alg. 9, invalidated)
   H5 an allocated block has its class's type, padding slots set, >= 1 object
@@ -33,11 +34,12 @@ class Dump:
     """A quiescent heap of M blocks and the classes' capacities, turned into
     raw dump bytes.  blocks[b] = (class or None, allocation word)."""
 
-    def __init__(self, M=130, caps=(64, 42)):
-        self.M, self.caps = M, list(caps)
+    def __init__(self, M=130, caps=(64, 42), stride=16):
+        self.M, self.caps, self.stride = M, list(caps), stride
         self.blocks = [(None, ONES)] * M
         self.type_override = {}
         self.extra_bits = []           # (bitmap, level, bit index) toggled after derivation
+        self.gap_words = []            # (bitmap, level, word index, offset 1..stride-1, value)
 
     def levels(self):
         words, n = [], self.M
@@ -66,7 +68,7 @@ class Dump:
         loff, off = [], 0
         for w in lw:
             loff.append(off)
-            off += (w + 7) // 8 * 8
+            off += (w + 7) // 8 * 8 * self.stride
         bitmap_words = (off + 31) // 32 * 32
         p = 4096
         off_status = p; p += 256
@@ -77,7 +79,7 @@ class Dump:
         off_scratch = p; scratch = 1024 + 4 * M; p += scratch
         off_data = (p + 4095) // 4096 * 4096
         buf = bytearray(off_data)
-        hdr = [heapcheck.MAGIC, 1, M, nc, 768, len(lw)]
+        hdr = [heapcheck.MAGIC, 2, M, nc, 768, len(lw)]
         struct.pack_into("<6Q", buf, 0, *hdr)
         struct.pack_into("<6Q", buf, 48, *(lw + [0] * (6 - len(lw))))
         struct.pack_into("<6Q", buf, 96, *(loff + [0] * (6 - len(loff))))
@@ -86,6 +88,7 @@ class Dump:
                          scratch, off_data, off_data)
         struct.pack_into("<16Q", buf, 224, *(self.caps + [0] * (16 - nc)))
         struct.pack_into("<16Q", buf, 352, *([1] * nc + [0] * (16 - nc)))
+        struct.pack_into("<I", buf, 2540, self.stride)
         for b, (t, w) in enumerate(self.blocks):
             ty = 0xFFFFFFFF if t is None else t
             ty = self.type_override.get(b, ty)
@@ -111,7 +114,10 @@ class Dump:
                     for k in range(64):
                         if 64 * i + k < len(v) and v[64 * i + k]:
                             word |= 1 << k
-                    struct.pack_into("<Q", buf, off_bitmaps + 8 * (bm * bitmap_words + loff[l] + i), word)
+                    struct.pack_into("<Q", buf, off_bitmaps + 8 * (bm * bitmap_words + loff[l] + i * self.stride),
+                                     word)
+        for (bm, l, i, k, v) in self.gap_words:
+            struct.pack_into("<Q", buf, off_bitmaps + 8 * (bm * bitmap_words + loff[l] + i * self.stride + k), v)
         return bytes(buf)
 
     def check(self):
@@ -136,6 +142,35 @@ def test_consistent_dump_passes_and_counts():
     assert s["live"] == [64 + 3 + 1 + 1, 1 + 42]
     assert s["blocks"] == [4, 2]
     assert s["free"] == 130 - 6
+
+
+@pytest.mark.parametrize("stride", [1, 2, 16])
+def test_word_stride_is_read_from_the_header(stride):
+    # the same heap laid out with its bitmap words 1, 2 or 16 words apart
+    # decodes to the same bitmaps and counts
+    d = consistent()
+    d.stride = stride
+    raw = heapcheck.RawHeap(d.to_bytes())
+    assert raw.stride == stride
+    assert raw.bits(1)[[0, 1, 2, 129]].all() and raw.bits(2)[[65, 66]].all()
+    assert heapcheck.check(raw)["live"] == [64 + 3 + 1 + 1, 1 + 42]
+
+
+def test_format_1_dump_is_dense():
+    d = consistent()
+    d.stride = 1
+    b = bytearray(d.to_bytes())
+    struct.pack_into("<Q", b, 8, 1)             # format 1 has no stride field
+    struct.pack_into("<I", b, 2540, 0)
+    assert heapcheck.RawHeap(bytes(b)).stride == 1
+    assert heapcheck.check(heapcheck.RawHeap(bytes(b)))["blocks"] == [4, 2]
+
+
+def test_h2_set_word_between_level_words_is_rejected():
+    d = consistent()
+    d.gap_words.append((3, 0, 1, 5, 1 << 3))    # active[0], level 0: a word between words 1 and 2
+    with pytest.raises(AssertionError, match="unused words"):
+        d.check()
 
 
 def test_h1_level1_bit_without_children_is_rejected():
