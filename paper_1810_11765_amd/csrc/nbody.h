@@ -284,7 +284,10 @@ __device__ __forceinline__ uint32_t d2_offset(float d2) { return __float_as_uint
 // added in order; otherwise (the body itself, an empty slot near a body, or
 // operands outside the range) the four entries go through the general
 // operations with each term taken or skipped by a select.
-constexpr uint32_t kTile = 16;
+#ifndef SMMO_NB_TILE
+#define SMMO_NB_TILE 32
+#endif
+constexpr uint32_t kTile = SMMO_NB_TILE;
 
 __global__ __launch_bounds__(256) void k_nbody_force(DevHeap h, uint32_t cls, const uint32_t* R,
                                                       const unsigned long long* rcount, smmo_nbody_args a) {
