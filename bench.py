@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--sweep-blocks", type=int, default=1 << 21)
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
-    p.add_argument("--suite", choices=["ablation", "linux-scalability", "heap-size", "autotune", "nbody"],
+    p.add_argument("--suite", choices=["ablation", "linux-scalability", "heap-size", "autotune", "nbody", "batch"],
                    help="run one of the allocator studies instead of the headline and print its JSON line")
     p.add_argument("--suite-steps", type=int, default=None, help="predator-prey steps of a suite run")
     p.add_argument("--tune-cache", default=None, help="JSON cache the autotune suite writes "
@@ -836,9 +836,48 @@ def run_suite(args, torch, workloads):
         res = autotune_suite(torch, workloads, args.tune_cache or TUNED_LAUNCH)
     elif args.suite == "nbody":
         res = {"workload": "n-body with merging, 262,144 bodies, seed 42", **nbody_sub(torch, workloads)}
+    elif args.suite == "batch":
+        res = batch_suite(torch)
     else:
         res = heap_size_suite(torch, workloads, args.suite_steps or 100)
+    if args.calib_copy:
+        res["calib_copy_bytes"] = calib_copy(torch)
     print(json.dumps({"suite": args.suite, **res}), flush=True)
+
+
+def calib_copy(torch):
+    """A plain 1 GiB device copy, 5 times: the reference the HBM byte
+    counters are scaled by."""
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return 1 << 30
+
+
+def batch_suite(torch, steps=200, count=256):
+    """Only the batched run of the 256 predator-prey instances (the tuned
+    launch shape, graph replay; the kernels the batch counters and trace
+    profiles cover), checked instance by instance against the default shape's
+    run."""
+    import numpy as np
+    from paper_1810_11765_amd import serve as sv
+    from paper_1810_11765_amd import smmo as S
+    from paper_1810_11765_amd import tune
+    reqs = sv.make_requests(seed=42, count=count)
+    tuned = {"wg_per_cu": 0, "steps_per_launch": 1, "lookups": 5, "block_objects": 64, "mode": S.BATCH_PHASED}
+    tuned.update(tune.load(TUNED_LAUNCH, "predator-prey batched %d instances %d steps" % (count, steps)) or {})
+    arena = S.Arena(max(sv.arena_bytes_for(reqs, b) for b in (64, tuned["block_objects"])))
+    base, t_base, _ = sv.run_batched(reqs, steps, arena, per_launch=1, graph=True)
+    res, dt, grid = sv.run_batched(reqs, steps, arena, per_launch=tuned["steps_per_launch"], graph=True,
+                                   wg_per_cu=tuned["wg_per_cu"], lookups=tuned["lookups"],
+                                   block_objects=tuned["block_objects"], mode=tuned["mode"])
+    same = all(all(np.array_equal(x, y) for x, y in zip(res[k][0], base[k][0])) for k in base)
+    status = max(r[1] for r in res.values())
+    return {"workload": f"predator-prey, {count} instances of side 64-1023, {steps} steps, batched", "launch": tuned,
+            "workgroups": grid, "ms": round(dt * 1e3, 2), "instance_steps_s": round(count * steps / dt, 1),
+            "default_shape_ms": round(t_base * 1e3, 2), "identical_to_default_shape": bool(same), "status": status}
 
 
 def cpu_baseline():
@@ -939,12 +978,7 @@ def main():
             _progress("predator-prey plain vs batched vs served")
             out["predator_prey_plain_vs_batched"] = batch_sub(torch)
     if args.calib_copy:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes"] = 1 << 30
+        out["calib_copy_bytes"] = calib_copy(torch)
     if not args.no_cpu_baseline:
         _progress("cpu baseline")
         out["cpu_baseline"] = cpu_baseline()
