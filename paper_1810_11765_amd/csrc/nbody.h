@@ -269,6 +269,11 @@ constexpr uint32_t kGmLo = 0x26800000u, kGmHi = 0x4E800000u;
 // workload, so that with G m = 0 its term is exactly +0 (adding it leaves a
 // sum unchanged: a sum that starts at +0 is never -0).
 constexpr float kFarPos = 1024.0f;
+// Coordinates below kBox in magnitude keep every d2 of two of them at most
+// 2^39 (|dx| <= 2^19 after rounding), inside the fast range's upper end, so a
+// tile whose entries and bodies are all inside needs only d2's lower end
+// checked per entry: the minimum of four d2 against 2^-40.
+constexpr float kBox = 262144.0f;
 
 // offset of d2's bit pattern from the range's start: the value is in the
 // range iff the (unsigned) offset is below kD2Hi - kD2Lo
@@ -283,11 +288,17 @@ __device__ __forceinline__ uint32_t d2_offset(float d2) { return __float_as_uint
 // the tile is), the four terms come from the fast sqrt and division and are
 // added in order; otherwise (the body itself, an empty slot near a body, or
 // operands outside the range) the four entries go through the general
-// operations with each term taken or skipped by a select.
+// operations with each term taken or skipped by a select.  When every
+// coordinate of the workgroup's bodies and of the tile is inside kBox, the
+// four d2 are checked through their minimum alone.
 #ifndef SMMO_NB_TILE
 #define SMMO_NB_TILE 32
 #endif
 constexpr uint32_t kTile = SMMO_NB_TILE;
+#ifndef SMMO_NB_BOX_GROUP
+#define SMMO_NB_BOX_GROUP 4
+#endif
+constexpr uint32_t kBoxGroup = SMMO_NB_BOX_GROUP;   // tile entries per check in a boxed tile (divides 64)
 
 __global__ __launch_bounds__(256) void k_nbody_force(DevHeap h, uint32_t cls, const uint32_t* R,
                                                       const unsigned long long* rcount, smmo_nbody_args a) {
@@ -309,6 +320,7 @@ __global__ __launch_bounds__(256) void k_nbody_force(DevHeap h, uint32_t cls, co
     const float xi = me ? nb_f(h, p.ox, ikey) : 0.0f;
     const float yi = me ? nb_f(h, p.oy, ikey) : 0.0f;
     float sx = 0.0f, sy = 0.0f;
+    const bool wg_box = __syncthreads_and(fabsf(xi) < kBox && fabsf(yi) < kBox) != 0;   // false for NaN
     // general form of one entry: skipped entries (an empty slot, or body i
     // itself) may produce inf or NaN in s, never used (a select keeps the sums)
     auto exact = [&](const float4& v) {
@@ -323,7 +335,7 @@ __global__ __launch_bounds__(256) void k_nbody_force(DevHeap h, uint32_t cls, co
     };
     for (uint64_t t0 = 0; t0 < r; t0 += kTile) {
         __syncthreads();
-        bool slow = false;
+        bool slow = false, far = false;
         for (uint32_t e = threadIdx.x; e < kTile * 64; e += blockDim.x) {
             const uint64_t jr = t0 + (e >> 6);
             const uint32_t sl = e & 63;
@@ -335,14 +347,46 @@ __global__ __launch_bounds__(256) void k_nbody_force(DevHeap h, uint32_t cls, co
                     v = make_float4(nb_f(h, p.ox, jk), nb_f(h, p.oy, jk), a.G * nb_f(h, p.om, jk),
                                     __int_as_float((int)(jk + 1)));
                     slow |= __float_as_uint(v.z) - kGmLo >= kGmHi - kGmLo;
+                    far |= !(fabsf(v.x) < kBox && fabsf(v.y) < kBox);
                 }
             }
             tile[e] = v;
         }
         const bool tile_slow = __syncthreads_or(slow) != 0;
+        const bool tile_box = wg_box && __syncthreads_or(far) == 0;
         const uint32_t ne = (uint32_t)((r - t0 < kTile ? r - t0 : kTile) * 64);   // a multiple of 64
         if (tile_slow) {
             for (uint32_t e = 0; e < ne; ++e) exact(tile[e]);
+            continue;
+        }
+        if (tile_box) {
+            for (uint32_t e = 0; e < ne; e += kBoxGroup) {
+                float4 v[kBoxGroup];
+                float dx[kBoxGroup], dy[kBoxGroup], d2[kBoxGroup];
+#pragma unroll
+                for (uint32_t k = 0; k < kBoxGroup; ++k) {
+                    v[k] = tile[e + k];
+                    dx[k] = v[k].x - xi;
+                    dy[k] = v[k].y - yi;
+                    d2[k] = dx[k] * dx[k] + dy[k] * dy[k];
+                }
+                float m = d2[0];
+#pragma unroll
+                for (uint32_t k = 1; k < kBoxGroup; ++k) m = fminf(m, d2[k]);
+                if (__all(m >= 0x1p-40f)) {
+                    float sk[kBoxGroup];
+#pragma unroll
+                    for (uint32_t k = 0; k < kBoxGroup; ++k) sk[k] = div_cr_fast(v[k].z, d2[k] * sqrt_cr_fast(d2[k]));
+#pragma unroll
+                    for (uint32_t k = 0; k < kBoxGroup; ++k) {
+                        sx = sx + sk[k] * dx[k];
+                        sy = sy + sk[k] * dy[k];
+                    }
+                } else {
+#pragma unroll
+                    for (uint32_t k = 0; k < kBoxGroup; ++k) exact(v[k]);
+                }
+            }
             continue;
         }
         for (uint32_t e = 0; e < ne; e += 4) {

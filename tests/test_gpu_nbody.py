@@ -188,6 +188,34 @@ def test_force_fallback_paths_against_ieee():
     assert np.array_equal(vy.view(np.uint32), ay.view(np.uint32))
 
 
+@pytest.mark.parametrize("edge", ["inside", "outside"])
+def test_force_coordinate_box_edge_against_ieee(edge):
+    """Tiles whose coordinates are all below 2^18 in magnitude check d2 only
+    against its lower end; bodies at +-(the largest float below 2^18) give
+    d2 near 2^38, the largest such a tile can hold, and a body at exactly
+    2^18 sends every tile holding it (and its own workgroup) back to the
+    per-entry range check.  The force phase alone equals the oracle's
+    accelerations bit for bit either way."""
+    say(f"force coordinate box, {edge}")
+    rng = np.random.default_rng(23)
+    n = 64 * 40 + 17
+    x = rng.uniform(-1, 1, n).astype(np.float32)
+    y = rng.uniform(-1, 1, n).astype(np.float32)
+    m = np.exp(rng.standard_normal(n)).astype(np.float32)
+    big = np.float32(262144.0) if edge == "outside" else np.nextafter(np.float32(262144.0), np.float32(0))
+    x[5], y[5] = big, big                          # in the first i-block and tile
+    x[1500], y[1500] = -big, -big
+    x[2000], y[2000] = big, -big
+    z = np.zeros(n, np.float32)
+    sim = W().NBody(n=n, init=(x, y, z, z.copy(), m), G=1.0, dt=1.0)
+    sim.populate()
+    sim.phase(34)                                      # FORCE only: v = a*1
+    _, _, _, vx, vy, _ = sim.state()
+    ax, ay = core.c4_accel(x, y, m, np.arange(n), G=1.0)
+    assert np.array_equal(vx.view(np.uint32), ax.view(np.uint32))
+    assert np.array_equal(vy.view(np.uint32), ay.view(np.uint32))
+
+
 def test_nbody_config_100_steps_against_oracle_goldens():
     """The configuration as stated: 262,144 bodies of seed 42, 100 steps.  At
     steps 1, 10 and 100 the survivors are compared with the oracle's values
