@@ -97,13 +97,13 @@ __device__ inline bool invalidate_block(const DevHeap& h, uint64_t bid) {
     return false;
 }
 
-// Block::deallocate for a mask of slots of class-T objects, then Alg. 2's
-// block state update.
-__device__ inline void dealloc_mask(const DevHeap& h, uint32_t T, uint64_t bid, uint64_t mask) {
+// Alg. 2's block state update after a deallocation of `mask` from block
+// `bid` of class T whose AND returned `before` (wave-uniform arguments).
+__device__ inline void dealloc_update(const DevHeap& h, uint32_t T, uint64_t bid, uint64_t mask, uint64_t before) {
     T = uni32(T);
     bid = uni64(bid);
     mask = uni64(mask);
-    const uint64_t before = w_and(&h.alloc[bid], ~mask);
+    before = uni64(before);
     if ((before & mask) != mask) w_set_status(h, SMMO_STATUS_CORRUPT);   // double free
     const bool first = before == kOnes;
     const bool empty = (before & ~mask) == h.cls_pad[T];
@@ -115,6 +115,14 @@ __device__ inline void dealloc_mask(const DevHeap& h, uint32_t T, uint64_t bid, 
         bm_set(h, bm_free(), bid);
         w_count(h, SMMO_CNT_BLOCK_FREE);
     }
+}
+
+// Block::deallocate for a mask of slots of class-T objects, then the state update.
+__device__ inline void dealloc_mask(const DevHeap& h, uint32_t T, uint64_t bid, uint64_t mask) {
+    T = uni32(T);
+    bid = uni64(bid);
+    mask = uni64(mask);
+    dealloc_update(h, T, bid, mask, w_and(&h.alloc[bid], ~mask));
 }
 
 // One piece of a coalesced allocation (Alg. 1 + Alg. 6), wave-uniform: find
@@ -242,16 +250,37 @@ __device__ __forceinline__ uint64_t wave_alloc(const DevHeap& h, uint32_t cls, b
 __device__ inline void wave_destroy(const DevHeap& h, uint64_t ref, bool want) {
     want = want && ref != 0;
     uint64_t pending = ballot(want);
+    if (!pending) return;
     const uint32_t lane = lane_id();
-    while (pending) {                         // one iteration per distinct block
+    // group the lanes by block: the lowest lane of a group holds its mask
+    uint64_t my_mask = 0, leaders = 0;
+    while (pending) {
         const uint32_t leader = ctz64(pending);
         const uint64_t lref = readlane64(ref, leader);
         const bool in = ((pending >> lane) & 1) && ref_block(ref) == ref_block(lref);
         const uint64_t grp = ballot(in);
         const uint64_t mask = wave_or(in ? (1ull << ref_slot(ref)) : 0ull);
-        dealloc_mask(h, ref_cls(lref), ref_block(lref), mask);
+        if (lane == leader) my_mask = mask;
+        leaders |= 1ull << leader;
         w_count(h, SMMO_CNT_FREE_OBJ, popc64(grp));
         pending &= ~grp;
+    }
+    // the groups' ANDs touch different blocks: one per leader lane, all in flight together
+    const bool lead = (leaders >> lane) & 1;
+    uint64_t before = 0;
+    if (lead) before = at_and(&h.alloc[ref_block(ref)], ~my_mask);
+    // a group needs the state update when the block was full (first free
+    // slot), may now hold only its padding (the slots left form a run at the
+    // top of the word: a superset of "empty" that needs no per-lane class),
+    // or when the AND found a slot already free; the update itself runs
+    // wave-uniform, one group at a time
+    const uint64_t left = before & ~my_mask;
+    const uint64_t inv = ~left;
+    const bool need = lead && (before == kOnes || (inv & (inv + 1)) == 0 || (before & my_mask) != my_mask);
+    for (uint64_t todo = ballot(need); todo; todo &= todo - 1) {
+        const uint32_t l = ctz64(todo);
+        const uint64_t r = readlane64(ref, l);
+        dealloc_update(h, ref_cls(r), ref_block(r), readlane64(my_mask, l), readlane64(before, l));
     }
 }
 
