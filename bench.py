@@ -344,7 +344,7 @@ def nbody_sub(torch, workloads, steps=2):
     # waves per SIMD): cycles one SIMD spends per wave-instruction, and the
     # force kernel's time if every SIMD issued its instructions back to back
     # at those costs (mix per interaction from the SQ_INSTS_VALU counter run:
-    # 30.1 VALU lane-instructions, one square root and one reciprocal among
+    # 29.1 VALU lane-instructions, one square root and one reciprocal among
     # them, the rest priced as fmac)
     import ctypes as C
     L = S.lib()
@@ -361,7 +361,7 @@ def nbody_sub(torch, workloads, steps=2):
         torch.cuda.synchronize()
         ms = min(t.ms(name))
         cyc[name] = ms * 1e-3 * CLOCK_HZ * SIMDS / (wgs * 4 * iters * 8)
-    per_inter = (30.1 - 2) * cyc["fmac"] + cyc["sqrt"] + cyc["rcp"]     # SIMD cycles per wave-interaction
+    per_inter = (29.1 - 2) * cyc["fmac"] + cyc["sqrt"] + cyc["rcp"]     # SIMD cycles per wave-interaction
     bound_ms = inter / 64 * per_inter / (SIMDS * CLOCK_HZ) * 1e3
     return {"bodies_live": n, "ms_per_step": round((sum(tm.ms("merge")) + sum(tm.ms("force")) + sum(tm.ms("move"))) / steps, 3),
             "force_ms": round(f, 3), "merge_ms": round(sum(tm.ms("merge")) / steps, 3),
