@@ -183,6 +183,36 @@ def test_publication_order_message_passing(blocks, rounds):
         S().check(L.smmo_check_publish_order(buf.data_ptr(), nbytes - 8, blocks + 1, rounds, 5, out.data_ptr(), stream))
 
 
+@pytest.mark.parametrize("block_objects,fraction,seed", [(64, 0.5, 1), (64, 1.0, 2), (32, 0.6, 3)])
+def test_destroy_by_handle_across_blocks(block_objects, fraction, seed):
+    """Destroys whose lanes hold handles of many blocks and of two classes at
+    once (a random permutation of every live handle, 64 to a wave): each
+    block group's deallocation goes out as one lane-parallel atomic, and only
+    the groups that need it take Alg. 2's state update (a full block becomes
+    active, an emptied block is invalidated and freed; with 32 objects per
+    block both classes have padding slots).  Afterwards every heap invariant
+    holds, each class has exactly its survivors, and a full destroy leaves
+    every block free (App. A.1, Alg. 2, 7, 9)."""
+    say(f"destroy by handle across blocks: {block_objects} objects per block, fraction {fraction}")
+    H = S().Heap([[4, 4, 4], [8, 8, 8, 8]], 8192, block_objects=block_objects)
+    H.parallel_alloc(0, 8192, 8, S().CTOR_NONE)
+    H.parallel_alloc(1, 4096, 8, S().CTOR_NONE)
+    r0, r1 = H.dump_refs(0), H.dump_refs(1)
+    assert len(r0) == 8192 * 8 and len(r1) == 4096 * 8
+    refs = np.concatenate([r0, r1])
+    perm = np.random.default_rng(seed).permutation(len(refs))
+    k = int(len(refs) * fraction)
+    gone = np.ascontiguousarray(refs[perm[:k]])
+    H.parallel_destroy(torch.from_numpy(gone.view(np.int64)).cuda(), k, 1)
+    keep = set(refs[perm[k:]].tolist())
+    left0 = int((S().ref_class(refs[perm[k:]]) == 0).sum())
+    summary = check_heap(H, expect_live=[left0, len(keep) - left0])
+    assert set(H.dump_refs(0).tolist()) | set(H.dump_refs(1).tolist()) == keep
+    if fraction == 1.0:
+        assert summary["blocks"] == [0, 0] and summary["free"] == 8192
+    H.close()
+
+
 def test_every_live_object_visited_exactly_once():
     say("visit")
     smmo = S()
