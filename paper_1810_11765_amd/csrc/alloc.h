@@ -272,15 +272,35 @@ __device__ inline void wave_destroy(const DevHeap& h, uint64_t ref, bool want) {
     // a group needs the state update when the block was full (first free
     // slot), may now hold only its padding (the slots left form a run at the
     // top of the word: a superset of "empty" that needs no per-lane class),
-    // or when the AND found a slot already free; the update itself runs
-    // wave-uniform, one group at a time
+    // or when the AND found a slot already free
     const uint64_t left = before & ~my_mask;
     const uint64_t inv = ~left;
-    const bool need = lead && (before == kOnes || (inv & (inv + 1)) == 0 || (before & my_mask) != my_mask);
-    for (uint64_t todo = ballot(need); todo; todo &= todo - 1) {
+    const bool first = lead && before == kOnes;
+    const bool full_update = lead && ((inv & (inv + 1)) == 0 || (before & my_mask) != my_mask);
+    // a group whose only update is FIRST sets its block's active bit here, all
+    // such groups in one atomic (their level-0 words are independent);
+    // Alg. 3's set goes on one level up only for a word that was empty, and
+    // a bit found still set (another wave's clear pending) takes the
+    // spinning form below
+    const bool quick = first && !full_update;
+    const uint64_t blk = ref_block(ref);
+    const uint64_t bit = 1ull << (blk & 63);
+    uint64_t prev0 = bit;
+    if (quick) prev0 = at_or(bm_word(h, bm_active(h, ref_cls(ref)), 0, blk >> 6), bit);
+    const bool settle = quick && (prev0 == 0 || (prev0 & bit));
+    // the rest runs wave-uniform, one group at a time
+    for (uint64_t todo = ballot(full_update || settle); todo; todo &= todo - 1) {
         const uint32_t l = ctz64(todo);
         const uint64_t r = readlane64(ref, l);
-        dealloc_update(h, ref_cls(r), ref_block(r), readlane64(my_mask, l), readlane64(before, l));
+        const uint32_t T = ref_cls(r);
+        const uint64_t b = ref_block(r);
+        if (!((readlane64((uint64_t)quick, l)) & 1)) {
+            dealloc_update(h, T, b, readlane64(my_mask, l), readlane64(before, l));
+        } else if (readlane64(prev0, l) == 0) {
+            bm_set_from(h, bm_active(h, T), 1, b >> 6);          // the word was empty: its parent bit
+        } else {
+            bm_set_from(h, bm_active(h, T), 0, b);               // the bit was still set: spin as Alg. 3
+        }
     }
 }
 
