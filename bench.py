@@ -757,7 +757,7 @@ def autotune_suite(torch, workloads, cache):
 
     def same_wator(a, b):
         return all(np.array_equal(x, y) for x, y in zip(a[0], b[0])) and a[1] == b[1] == 0
-    rec = tune.search(wator, {"block_objects": [64, 32], "lookups": [5, 3, 8], "doall_waves_per_cu": [32, 48, 64],
+    rec = tune.search(wator, {"block_objects": [64, 32], "lookups": [5, 3, 8], "doall_waves_per_cu": [32, 24, 48, 64],
                               "doall_units": [16384, 4096, 65536]}, reps=3, equal=same_wator)
     tune.save(cache, "predator-prey 1024x1024 100 steps", rec)
     out["predator_prey"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}
@@ -787,7 +787,7 @@ def autotune_suite(torch, workloads, cache):
 
     def same_life(a, b):
         return all(np.array_equal(x, y) for x, y in zip(a[0], b[0])) and a[1] == b[1] == 0
-    rec = tune.search(life, {"lookups": [5, 3, 8, 12, 16], "doall_waves_per_cu": [32, 16, 48, 64],
+    rec = tune.search(life, {"lookups": [5, 3, 8, 12, 16], "doall_waves_per_cu": [32, 16, 24, 48, 64],
                              "doall_units": [16384, 4096, 8192, 32768, 65536]}, reps=5, equal=same_life)
     tune.save(cache, "life-like 512x512 200 steps", rec)
     out["life"] = {k: rec[k] for k in ("default", "default_s", "best", "best_s", "speedup")}

@@ -156,9 +156,10 @@ struct Obj {
 };
 
 // Parallel do-all (Sec. 3.7), enumeration fused in: the L0 words of
-// allocated[cls] are cut into units of 64 >> s_log2 block bits; a wave takes a
-// unit (grid-stride), walks its set bits in ascending order (the bitmap scan
-// is the compaction) and runs the method on each block with lane = slot, so
+// allocated[cls] are cut into units of 64 >> s_log2 block bits; a wave takes
+// units grid-stride (the bitmap words of up to 64 of them in one round trip),
+// walks the set bits of each in ascending order (the bitmap scan is the
+// compaction) and runs the method on each block with lane = slot, so
 // every field access of the wave is one contiguous SOA segment.  Objects the
 // method creates are not visited: with M::kSnapshot the wave reads the
 // iteration word written by k_snapshot (blocks initialized meanwhile have it
@@ -221,34 +222,54 @@ __global__ __launch_bounds__(kBlockThreads) void k_doall(DevHeap h, uint32_t cls
         }
         return;
     }
-    for (uint64_t u = wave; u < nunits; u += nwaves) {
-        const uint64_t w = u >> s_log2;
-        const uint32_t first = (uint32_t)(u & ((1u << s_log2) - 1)) * span;   // first block bit of the unit
-        const uint64_t my_blk = (w << 6) + first + lane;                       // lane l: block first + l
-        const bool mine = lane < span && my_blk < h.M;
-        uint64_t my_word = 0, word;
-        if (!kSnap) {
-            // The class gains no block during this do-all and a block leaves
-            // only through its own wave, so the words can be fetched together
-            // with the bitmap word; words of blocks whose bit is clear are
-            // never used.
-            if (mine) my_word = h.alloc[my_blk];
-            word = l0[w * kBmStride] & (span_mask << first);
-        } else {
-            // Blocks may be (re)initialized meanwhile: read the bitmap word
-            // first, then the iteration words of its set bits.
-            word = at_load(l0 + w * kBmStride) & (span_mask << first);
-            if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
+    // The wave's units are wave + k * nwaves.  Lane k reads the bitmap word
+    // of the k-th (64 units per round trip), so a unit with no block of the
+    // class costs nothing more and a small grid does not pay a dependent load
+    // per empty unit; the wave then visits the units that hold blocks.
+    for (uint64_t base = wave; base < nunits; base += 64 * nwaves) {
+        const uint64_t uk = base + (uint64_t)lane * nwaves;
+        uint64_t wk = 0;
+        if (uk < nunits) {
+            const uint64_t w = uk >> s_log2;
+            const uint32_t first = (uint32_t)(uk & ((1u << s_log2) - 1)) * span;
+            wk = (kSnap ? at_load(l0 + w * kBmStride) : l0[w * kBmStride]) & (span_mask << first);
         }
-        while (word) {
-            const uint32_t b = ctz64(word);
-            word &= word - 1;
-            const uint64_t bid = (w << 6) | b;
-            const uint64_t live = (uint64_t)__shfl((unsigned long long)my_word, (int)(b - first), 64) & valid;
-            Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
-                  wave_seed(wave, bid)};
-            M::run(o, prep, a);
-            if (kRecord && lane == 0) h.iter[bid] = live;
+        // the first unit's allocation words travel with the bitmap words: the
+        // class gains no block during this do-all and a block leaves only
+        // through its own wave, so they are current, and the words of blocks
+        // whose bit is clear are never used
+        const uint32_t first0 = (uint32_t)(base & ((1u << s_log2) - 1)) * span;
+        const uint64_t blk0 = ((base >> s_log2) << 6) + first0 + lane;
+        uint64_t word0 = 0;
+        if (!kSnap && lane < span && blk0 < h.M) word0 = h.alloc[blk0];
+        for (uint64_t todo = ballot(wk != 0); todo; todo &= todo - 1) {
+            const uint32_t k = ctz64(todo);
+            const uint64_t u = base + (uint64_t)k * nwaves;
+            const uint64_t w = u >> s_log2;
+            const uint32_t first = (uint32_t)(u & ((1u << s_log2) - 1)) * span;   // first block bit of the unit
+            const uint64_t my_blk = (w << 6) + first + lane;                       // lane l: block first + l
+            const bool mine = lane < span && my_blk < h.M;
+            uint64_t word = readlane64(wk, k);
+            uint64_t my_word = 0;
+            if (!kSnap) {
+                if (k == 0) my_word = word0;
+                else if (mine) my_word = h.alloc[my_blk];
+            } else {
+                // blocks may be (re)initialized meanwhile: the iteration words
+                // of the bits the bitmap word showed (a block initialized
+                // since has its word zeroed)
+                if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
+            }
+            while (word) {
+                const uint32_t b = ctz64(word);
+                word &= word - 1;
+                const uint64_t bid = (w << 6) | b;
+                const uint64_t live = (uint64_t)__shfl((unsigned long long)my_word, (int)(b - first), 64) & valid;
+                Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
+                      wave_seed(wave, bid)};
+                M::run(o, prep, a);
+                if (kRecord && lane == 0) h.iter[bid] = live;
+            }
         }
     }
 }
