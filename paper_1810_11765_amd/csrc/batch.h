@@ -108,28 +108,46 @@ __device__ inline void batch_phase(const DevHeap& h, uint32_t cls, const smmo_wa
     const uint64_t unit_mask = (1ull << span) - 1;
     const uint64_t nunits = h.level_words[0] << per_word_log2;
     const typename M::Prep prep = M::prepare(h, cls, a);
-    for (uint64_t u = wave_rank; u < nunits; u += nwaves) {
-        const uint64_t w = u >> per_word_log2;
-        const uint32_t first = (uint32_t)(u & ((1u << per_word_log2) - 1)) << unit_log2;
-        const uint64_t my_blk = (w << 6) + first + lane;
-        const bool mine = lane < span && my_blk < h.M;
-        uint64_t my_word = 0, word;
-        if (!M::kSnapshot) {       // no block of the class appears during a plan phase
-            if (mine) my_word = at_load(&h.alloc[my_blk]);
-            word = at_load(l0 + w * kBmStride) & (unit_mask << first);
-        } else {
-            word = at_load(l0 + w * kBmStride) & (unit_mask << first);
-            if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
+    // as in the do-all: lane k reads the bitmap word of the wave's k-th unit
+    // (64 per round trip, with the first unit's allocation words in a plan
+    // phase), and the wave visits only the units that hold blocks
+    for (uint64_t base = wave_rank; base < nunits; base += 64ull * nwaves) {
+        const uint64_t uk = base + (uint64_t)lane * nwaves;
+        uint64_t wk = 0;
+        if (uk < nunits) {
+            const uint64_t w = uk >> per_word_log2;
+            const uint32_t first = (uint32_t)(uk & ((1u << per_word_log2) - 1)) << unit_log2;
+            wk = at_load(l0 + w * kBmStride) & (unit_mask << first);
         }
-        while (word) {
-            const uint32_t b = ctz64(word);
-            word &= word - 1;
-            const uint64_t bid = (w << 6) | b;
-            const uint64_t live = (uint64_t)__shfl((unsigned long long)my_word, (int)(b - first), 64) & valid;
-            Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
-                  wave_seed(((uint64_t)a.step << 20) ^ wave_rank, bid)};
-            M::run(o, prep, a);
-            if (snap && lane == 0) h.iter[bid] = at_load(&h.alloc[bid]) & valid;
+        const uint32_t first0 = (uint32_t)(base & ((1u << per_word_log2) - 1)) << unit_log2;
+        const uint64_t blk0 = ((base >> per_word_log2) << 6) + first0 + lane;
+        uint64_t word0 = 0;
+        if (!M::kSnapshot && lane < span && blk0 < h.M) word0 = at_load(&h.alloc[blk0]);   // no block of the class appears during a plan phase
+        for (uint64_t todo = ballot(wk != 0); todo; todo &= todo - 1) {
+            const uint32_t k = ctz64(todo);
+            const uint64_t u = base + (uint64_t)k * nwaves;
+            const uint64_t w = u >> per_word_log2;
+            const uint32_t first = (uint32_t)(u & ((1u << per_word_log2) - 1)) << unit_log2;
+            const uint64_t my_blk = (w << 6) + first + lane;
+            const bool mine = lane < span && my_blk < h.M;
+            uint64_t word = readlane64(wk, k);
+            uint64_t my_word = 0;
+            if (!M::kSnapshot) {
+                if (k == 0) my_word = word0;
+                else if (mine) my_word = at_load(&h.alloc[my_blk]);
+            } else {
+                if (mine && ((word >> (first + lane)) & 1)) my_word = at_load(&h.iter[my_blk]);
+            }
+            while (word) {
+                const uint32_t b = ctz64(word);
+                word &= word - 1;
+                const uint64_t bid = (w << 6) | b;
+                const uint64_t live = (uint64_t)__shfl((unsigned long long)my_word, (int)(b - first), 64) & valid;
+                Obj o{h, cls, bid, lane, ((live >> lane) & 1) != 0, h.data + bid * h.block_bytes,
+                      wave_seed(((uint64_t)a.step << 20) ^ wave_rank, bid)};
+                M::run(o, prep, a);
+                if (snap && lane == 0) h.iter[bid] = at_load(&h.alloc[bid]) & valid;
+            }
         }
     }
 }
